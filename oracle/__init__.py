@@ -1,0 +1,36 @@
+"""FP64 CPU oracle for decentralized feedforward L-MMSE equalisation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute anything in this package: only the test-suite, the smoke check of the
+graft entry point and the ``cpu_baseline`` leg of ``bench.py`` use it.
+
+The oracle is a plain, slow, obviously-correct restatement of what the paper
+defines (Jeon, Li, Cavallaro, Studer, "Decentralized Equalization with
+Feedforward Architectures for Massive MU-MIMO"), computed in complex128 from
+the very complex64 inputs the GPU receives.  It shares no code with the HIP
+path: it uses NumPy library primitives (matmul, solve, inv) as steps and does
+no blocking, fusion or reordering beyond what the formulas state.
+
+Modules
+-------
+lmmse        forward PD / FD L-MMSE (Sections II-C, III-A, IV-A, IV-B)
+adjoint      analytic gradients of both equalisers (derived, not in the paper)
+asymptotics  large-system SINR closed forms (Theorem 1, Corollary 1, Lemma 5)
+
+Pins: every function is checked in ``tests/test_oracle_*.py`` against values
+the paper's mathematics fixes (identities, closed forms, worked examples,
+finite differences, Monte-Carlo error variances).  Nothing here is "parity
+unpinned".
+"""
+from .lmmse import (local_statistics, lmmse_estimate, lmmse_error_variance,
+                    lmmse_error_variance_simplified, cond_estimate, eq_pd, eq_fd,
+                    optimal_fusion_weights, eq_centralized)
+from .adjoint import pd_backward, fd_backward
+from .asymptotics import (sinr_pd_lmmse, sinr_fd_lmmse, tse_hanly_lmmse_sigma2)
+
+__all__ = [
+    "local_statistics", "lmmse_estimate", "lmmse_error_variance",
+    "lmmse_error_variance_simplified", "cond_estimate", "eq_pd", "eq_fd",
+    "optimal_fusion_weights", "eq_centralized", "pd_backward", "fd_backward",
+    "sinr_pd_lmmse", "sinr_fd_lmmse", "tse_hanly_lmmse_sigma2",
+]
