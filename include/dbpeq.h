@@ -1,0 +1,187 @@
+/*
+ * dbpeq.h -- C ABI of libdbpeq.so: decentralized feedforward L-MMSE
+ * equalisation for the massive MU-MIMO uplink on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section II-A, eq. (iorelation)): y = H s0 + n with H in C^{B x U}
+ * perfectly known, n ~ CN(0, N0 I), symbols of energy E_s (eq. (prior)).  The
+ * B antenna rows are split into C contiguous clusters (Section II-B,
+ * eq. (perclusterInOutrelation)).  Every call processes W independent systems
+ * ("subcarriers") that share (B, U, partition, N0).
+ *
+ * Memory layout (all DEVICE pointers, owned by the caller, complex values
+ * interleaved re/im as in torch.complex64, row-major, no padding):
+ *   H      [W][B][U]   eq_c32     system matrices; cluster c owns rows
+ *                                 cluster_off[c] .. cluster_off[c+1]-1
+ *   y      [W][B]      eq_c32     receive vectors
+ *   z      [W][U]      eq_c32     equalised estimate (output)
+ *   sigma2 [W][U]      float      post-equalisation error variance (output)
+ *   nu     [W][C][U]   float      FD fusion weights (input, optional)
+ *   info   PD: [W], FD: [W][C]    int32 status per system / cluster (output)
+ *
+ * Error behaviour.  Arguments are validated on the host before any HIP call;
+ * on failure a call returns EQ_EINVAL (or EQ_ENOTSUP / EQ_EWORKSPACE) and has
+ * no device side effects.  Calls are asynchronous and stream-ordered
+ * (`stream` is a hipStream_t, NULL = the null stream).  Numerical trouble is
+ * reported per system in `info`:
+ *     0            success
+ *     k > 0        leading minor k of (G + rho I) not positive definite even
+ *                  after the FP64 re-solve; that system's outputs are NaN
+ *    -1            a non-finite value in the system's H or y; outputs NaN
+ *   | EQ_INFO_FP64 (bit 30) the system (PD) or cluster (FD) had an estimated
+ *                  condition number above EQ_COND_LIMIT or a failed FP32/BF16
+ *                  pivot, and its subcarrier was re-solved in FP64 on the GPU
+ *                  (informational, not an error).
+ * No exceptions and no global mutable state cross the ABI; concurrent calls on
+ * different streams are safe when they use different workspaces.
+ */
+#ifndef DBPEQ_H
+#define DBPEQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EQ_ABI_VERSION 1
+#define EQ_MAX_U 32          /* users per system */
+#define EQ_MAX_B 65535       /* antennas per system */
+#define EQ_MAX_C 1024        /* clusters per system */
+#define EQ_INFO_FP64 (1 << 30)
+#define EQ_COND_LIMIT 1.0e4f
+
+typedef struct { float re, im; } eq_c32;   /* == one torch.complex64 element */
+
+typedef enum {
+  EQ_OK = 0,
+  EQ_EINVAL = -1,      /* invalid argument (shape, pointer, partition, N0 ...) */
+  EQ_ENOTSUP = -2,     /* valid but unsupported (U > EQ_MAX_U, ...)            */
+  EQ_EHIP = -3,        /* a HIP runtime call failed                             */
+  EQ_EWORKSPACE = -4,  /* workspace missing or smaller than eq_workspace_size   */
+  EQ_ENOMEM = -5       /* plan creation could not allocate device memory        */
+} eq_status;
+
+typedef enum {
+  /* Gram + matched filter in FP32 (Gram on FP32 MFMA), FP32 solves. */
+  EQ_FP32 = 0,
+  /* Gram on BF16 MFMA with FP32 accumulation, FP32 matched filter and solves,
+     then one refinement step with the FP32 residual y - H z. */
+  EQ_BF16_REFINE = 1,
+  /* As EQ_BF16_REFINE with each operand split into a BF16 high and low part
+     (three BF16 products hi*hi + hi*lo + lo*hi per Gram term). */
+  EQ_BF16X3_REFINE = 2
+} eq_precision;
+
+/* Shared description of a batch of W systems. */
+typedef struct {
+  int32_t W;                  /* systems in the batch, >= 0 (0 = no-op)          */
+  int32_t B;                  /* BS antennas, 1..EQ_MAX_B                        */
+  int32_t U;                  /* single-antenna users, 1..EQ_MAX_U               */
+  int32_t C;                  /* clusters, 1..min(B, EQ_MAX_C)                   */
+  const int32_t *cluster_off; /* HOST array of C+1 offsets,
+                                 0 = off[0] < off[1] < ... < off[C] = B          */
+  float n0;                   /* noise variance per complex entry, finite, > 0   */
+  float es;                   /* symbol energy E_s, finite, > 0 (normally 1)     */
+  int32_t precision;          /* an eq_precision value                            */
+} eq_problem;
+
+/* Bytes of device workspace the forward calls need for this problem (the
+   list of systems routed to the FP64 re-solve).  The caller allocates it;
+   the library never allocates device memory in eq_pd / eq_fd. */
+size_t eq_workspace_size(const eq_problem *p);
+
+/* Partially decentralised L-MMSE (Section II-C; Section III-A).
+   Each cluster forms G_c = H_c^H H_c and y_c^MRC = H_c^H y_c; the adder tree
+   sums them (eq. (fullMRC)); the centralised unit returns
+   z = (G + rho I)^{-1} y^MRC with rho = N0/E_s and its error variance
+   sigma2 = N0 diag((G + rho I)^{-1}), which is the Section III-A variance
+   evaluated at rho = N0/E_s.  sigma2 and info may be NULL. */
+eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
+                eq_c32 *z, float *sigma2, int32_t *info,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Fully decentralised L-MMSE (Section II-D; Section IV).
+   Each cluster equalises locally, z_c = (G_c + rho I)^{-1} y_c^MRC and
+   sigma2_c = N0 diag((G_c + rho I)^{-1}); the fusion tree returns
+   z_u = sum_c nu_{c,u} z_{c,u} (eq. (fusionrule)).  With nu == NULL the
+   weights are the optimal ones of Lemma 1 (eq. (opt_fusion)) and
+   sigma2_u = (sum_c 1/sigma2_{c,u})^{-1} (Theorem 3); with user weights
+   nu [W][C][U] they are used as given and sigma2_u = sum_c nu^2 sigma2_{c,u}.
+   sigma2 and info (size [W][C]) may be NULL. */
+eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
+                const float *nu, eq_c32 *z, float *sigma2, int32_t *info,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace the backward calls need. */
+size_t eq_backward_workspace_size(const eq_problem *p);
+
+/* Adjoint of eq_pd (not in the paper; derived from its forward map).  Given
+   upstream gradients gz [W][U] (complex, d/dRe + i d/dIm, may be NULL = 0)
+   and gs [W][U] (of sigma2, may be NULL = 0), writes
+     gH [W][B][U] = (y - H z) lambda^H - H lambda z^H - 2 N0 H Q,
+     gy [W][B]    = H lambda,
+     gn0 (one device float) = sum_w [ -Re(z^H lambda)/E_s + sum_u gs_u d_u - N0 tr(Q)/E_s ],
+   with lambda = A^{-1} gz, Q = A^{-1} diag(gs) A^{-1}, d = diag(A^{-1}),
+   A = G + rho I, all recomputed from H, y (FP32; `precision` is ignored).
+   gH, gy, gn0 may each be NULL to skip that output. */
+eq_status eq_pd_backward(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
+                         const eq_c32 *gz, const float *gs,
+                         eq_c32 *gH, eq_c32 *gy, float *gn0,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Adjoint of eq_fd.  The per-cluster maps are differentiated as in
+   eq_pd_backward with upstream gradients g_{z_c} = nu_c * gz and g_{sigma2_c}
+   from the fusion rule; with optimal weights the dependence of nu on sigma2_c
+   is included.  gnu [W][C][U] (may be NULL) receives dL/dnu when nu is given
+   (it must be NULL when nu is NULL). */
+eq_status eq_fd_backward(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
+                         const float *nu, const eq_c32 *gz, const float *gs,
+                         eq_c32 *gH, eq_c32 *gy, float *gn0, float *gnu,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- Ragged batches: thousands of independent systems of uneven shape ---- */
+
+/* One system of a ragged batch.  Offsets are in ELEMENTS of the pools given
+   to eq_plan_execute: H at Hpool + h_off ([B][U] row-major), y at ypool + y_off
+   ([B]), z / sigma2 at zpool / s2pool + z_off ([U]).  Its C cluster sizes are
+   cluster_sizes[clus_first .. clus_first + C - 1] (they must sum to B). */
+typedef struct {
+  int64_t h_off, y_off, z_off;
+  int32_t B, U, C, clus_first;
+  float n0;
+  int32_t _reserved;
+} eq_sys;
+
+typedef struct eq_plan eq_plan;
+
+/* Validates the descriptors, sorts the systems into cost-ordered work items,
+   uploads the descriptor table (the plan owns this device memory) and loads
+   the tile choice from the autotune cache (`tune_cache_path`, NULL = the
+   DBPEQ_TUNE_CACHE environment variable, else no cache).  fd selects FD
+   (1) or PD (0).  Returns EQ_ENOMEM if the table cannot be allocated. */
+eq_status eq_plan_create(eq_plan **out, const eq_sys *host_desc, int32_t nsys,
+                         const int32_t *host_cluster_sizes, int32_t n_cluster_sizes,
+                         int32_t fd, int32_t precision, float es,
+                         const char *tune_cache_path);
+
+/* Equalises every system of the plan: z, sigma2 (may be NULL) and info
+   ([nsys], may be NULL).  The first call on a plan autotunes (when the cache
+   has no entry) and captures one persistent launch into a hipGraph; later
+   calls with the same pools and stream replay the graph.  Stream-ordered. */
+eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypool,
+                          eq_c32 *zpool, float *s2pool, int32_t *info, void *stream);
+
+/* Tile choice of the plan: per U class (0: U <= 16, 1: U <= 32) the tuned
+   persistent grid size in waves (out_waves[2]) and the total tasks. */
+eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_waves, int32_t *out_tasks);
+
+eq_status eq_plan_destroy(eq_plan *plan);
+
+const char *eq_status_string(eq_status s);
+int32_t eq_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBPEQ_H */

@@ -1,0 +1,163 @@
+"""Thin Python binding of libdbpeq.so (ctypes; argument marshalling only).
+
+Every step of the equaliser runs in the library's HIP kernels; this module
+checks tensor placement / dtype / shape, allocates outputs and workspace with
+PyTorch (device memory and streams only) and calls the C ABI declared in
+include/dbpeq.h on the current HIP stream.  If the library is not built the
+calls raise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdbpeq.so")
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported problem size",
+          -3: "HIP runtime error", -4: "workspace missing or too small",
+          -5: "device allocation failed"}
+INFO_FP64 = 1 << 30
+
+
+class EqError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class EqProblem(ctypes.Structure):
+    _fields_ = [("W", c_int32), ("B", c_int32), ("U", c_int32), ("C", c_int32),
+                ("cluster_off", POINTER(c_int32)), ("n0", c_float), ("es", c_float),
+                ("precision", c_int32)]
+
+
+class EqSys(ctypes.Structure):
+    _fields_ = [("h_off", c_int64), ("y_off", c_int64), ("z_off", c_int64),
+                ("B", c_int32), ("U", c_int32), ("C", c_int32), ("clus_first", c_int32),
+                ("n0", c_float), ("_reserved", c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point of include/dbpeq.h
+SIGNATURES = [
+    ("eq_abi_version", c_int32, []),
+    ("eq_status_string", c_char_p, [c_int32]),
+    ("eq_workspace_size", c_size_t, [POINTER(EqProblem)]),
+    ("eq_backward_workspace_size", c_size_t, [POINTER(EqProblem)]),
+    ("eq_pd", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                        c_void_p, c_size_t, c_void_p]),
+    ("eq_fd", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                        c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_pd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_fd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_size_t, c_void_p]),
+    ("eq_plan_create", c_int32, [POINTER(c_void_p), POINTER(EqSys), c_int32, POINTER(c_int32),
+                                 c_int32, c_int32, c_int32, c_float, c_char_p]),
+    ("eq_plan_execute", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p]),
+    ("eq_plan_describe", c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    ("eq_plan_destroy", c_int32, [c_void_p]),
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdbpeq.so (built in-tree by paper_1808_04473_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1808_04473_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(fn: str, st: int):
+    if st != 0:
+        raise EqError(fn, st)
+
+
+def make_problem(W, B, U, cluster_off, n0, es=1.0, precision="fp32"):
+    """EqProblem plus the host offset array that must outlive the call."""
+    off = np.ascontiguousarray(np.asarray(cluster_off, dtype=np.int32))
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p = EqProblem(int(W), int(B), int(U), int(len(off) - 1),
+                  off.ctypes.data_as(POINTER(c_int32)), float(n0), float(es), prec)
+    return p, off
+
+
+def _check_inputs(H, y):
+    if not (isinstance(H, torch.Tensor) and isinstance(y, torch.Tensor)):
+        raise TypeError("H and y must be torch tensors")
+    if H.device.type != "cuda" or y.device.type != "cuda":
+        raise ValueError("H and y must be on a HIP device (no CPU fallback)")
+    if H.dtype != torch.complex64 or y.dtype != torch.complex64:
+        raise TypeError("H and y must be complex64")
+    if H.dim() != 3 or y.dim() != 2 or H.shape[0] != y.shape[0] or H.shape[1] != y.shape[1]:
+        raise ValueError(f"shapes H {tuple(H.shape)} / y {tuple(y.shape)} are not [W][B][U] / [W][B]")
+    return H.contiguous(), y.contiguous()
+
+
+def workspace(prob: EqProblem, device) -> torch.Tensor:
+    lib = load_library()
+    n = lib.eq_workspace_size(ctypes.byref(prob))
+    return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+
+
+def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False):
+    """Partially decentralised L-MMSE of W systems: (z [W][U] c64, sigma2 [W][U] f32)."""
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
+    s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+    info = torch.empty((W,), dtype=torch.int32, device=H.device)
+    ws = workspace(prob, H.device)
+    st = lib.eq_pd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info),
+                   _ptr(ws), ws.numel(), _stream())
+    _check("eq_pd", st)
+    return (z, s2, info) if return_info else (z, s2)
+
+
+def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False):
+    """Fully decentralised L-MMSE; nu [W][C][U] float32 user weights or None (optimal)."""
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    C = prob.C
+    if nu is not None:
+        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
+            raise ValueError("nu must be float32 [W][C][U] on the same device")
+        nu = nu.contiguous()
+    z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
+    s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+    info = torch.empty((W, C), dtype=torch.int32, device=H.device)
+    ws = workspace(prob, H.device)
+    st = lib.eq_fd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(nu), _ptr(z), _ptr(s2), _ptr(info),
+                   _ptr(ws), ws.numel(), _stream())
+    _check("eq_fd", st)
+    return (z, s2, info) if return_info else (z, s2)

@@ -1,0 +1,111 @@
+// C ABI of libdbpeq.so: host-side validation and dispatch.  Every argument is
+// checked before the first HIP call, so invalid calls have no device effects.
+#include <math.h>
+#include <string.h>
+
+#include "eq_common.h"
+
+using namespace dbpeq;
+
+namespace {
+
+constexpr size_t kWsHeader = 256;
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+eq_status check_problem(const eq_problem *p) {
+  if (!p) return EQ_EINVAL;
+  if (p->W < 0 || p->B < 1 || p->U < 1 || p->C < 1) return EQ_EINVAL;
+  if (p->B > EQ_MAX_B || p->C > EQ_MAX_C) return EQ_ENOTSUP;
+  if (p->C > p->B) return EQ_EINVAL;
+  if (p->U > EQ_MAX_U) return EQ_ENOTSUP;
+  if (!p->cluster_off) return EQ_EINVAL;
+  if (p->cluster_off[0] != 0 || p->cluster_off[p->C] != p->B) return EQ_EINVAL;
+  for (int c = 0; c < p->C; ++c)
+    if (p->cluster_off[c + 1] <= p->cluster_off[c]) return EQ_EINVAL;
+  if (!isfinite(p->n0) || !(p->n0 > 0.f)) return EQ_EINVAL;
+  if (!isfinite(p->es) || !(p->es > 0.f)) return EQ_EINVAL;
+  if (p->precision < EQ_FP32 || p->precision > EQ_BF16X3_REFINE) return EQ_EINVAL;
+  const float rho = p->n0 / p->es;
+  if (!isfinite(rho) || !(rho > 0.f)) return EQ_EINVAL;
+  return EQ_OK;
+}
+
+size_t ws_bytes_for(const eq_problem *p) {
+  const size_t list = (size_t)(p->W > 0 ? p->W : 1) * sizeof(int32_t);
+  return kWsHeader + ((list + 255) / 256) * 256;
+}
+
+void fill_fwd(FwdArgs &a, const eq_problem *p) {
+  memset(&a, 0, sizeof(a));
+  a.W = p->W;
+  a.B = p->B;
+  a.U = p->U;
+  a.C = p->C;
+  a.n0 = p->n0;
+  a.es = p->es;
+  a.rho = p->n0 / p->es;
+  for (int c = 0; c <= p->C; ++c) a.off[c] = (uint16_t)p->cluster_off[c];
+  a.spw = fd_spw(ut_for(p->U), p->C);
+}
+
+eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                  eq_c32 *z, float *s2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  eq_status st = check_problem(p);
+  if (st != EQ_OK) return st;
+  if (p->W == 0) return EQ_OK;
+  if (!H || !y || !z) return EQ_EINVAL;
+  if (!aligned(H, 8) || !aligned(y, 8) || !aligned(z, 8)) return EQ_EINVAL;
+  if ((s2 && !aligned(s2, 4)) || (info && !aligned(info, 4)) || (nu && !aligned(nu, 4))) return EQ_EINVAL;
+  if (!ws || ws_bytes < ws_bytes_for(p) || !aligned(ws, 4)) return EQ_EWORKSPACE;
+  FwdArgs a;
+  fill_fwd(a, p);
+  a.H = reinterpret_cast<const float2 *>(H);
+  a.y = reinterpret_cast<const float2 *>(y);
+  a.nu = fd ? nu : nullptr;
+  a.z = reinterpret_cast<float2 *>(z);
+  a.s2 = s2;
+  a.info = info;
+  a.fb_count = reinterpret_cast<int32_t *>(ws);
+  a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (launch_zero_i32(a.fb_count, 1, s) != hipSuccess) return EQ_EHIP;
+  if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
+  if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
+  return EQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t eq_abi_version(void) { return EQ_ABI_VERSION; }
+
+const char *eq_status_string(eq_status s) {
+  switch (s) {
+    case EQ_OK: return "ok";
+    case EQ_EINVAL: return "invalid argument";
+    case EQ_ENOTSUP: return "unsupported problem size";
+    case EQ_EHIP: return "HIP runtime error";
+    case EQ_EWORKSPACE: return "workspace missing or too small";
+    case EQ_ENOMEM: return "device allocation failed";
+  }
+  return "unknown status";
+}
+
+size_t eq_workspace_size(const eq_problem *p) {
+  if (check_problem(p) != EQ_OK) return 0;
+  return ws_bytes_for(p);
+}
+
+eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *sigma2,
+                int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return forward(p, false, H, y, nullptr, z, sigma2, info, ws, ws_bytes, stream);
+}
+
+eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, const float *nu, eq_c32 *z,
+                float *sigma2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return forward(p, true, H, y, nu, z, sigma2, info, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal definitions shared by the host launcher code and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dbpeq.h"
+
+namespace dbpeq {
+
+enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+
+// Forward launch arguments (passed by value; the cluster table lives in the
+// kernel-argument segment, so no device-side copy of the host partition is
+// needed and the launch can be captured into a graph).
+struct FwdArgs {
+  const float2 *H;
+  const float2 *y;
+  const float *nu;      // [W][C][U] or nullptr (optimal weights)
+  float2 *z;
+  float *s2;            // may be nullptr
+  int32_t *info;        // may be nullptr
+  int32_t *fb_count;    // FP64 re-solve queue (workspace)
+  int32_t *fb_list;
+  int32_t W, B, U, C;
+  float n0, rho, es;
+  int32_t spw;          // FD: subcarriers per wave
+  uint16_t off[EQ_MAX_C + 1];
+};
+
+// Backward launch arguments.
+struct BwdArgs {
+  const float2 *H;
+  const float2 *y;
+  const float *nu;
+  const float2 *gz;     // may be nullptr
+  const float *gs;      // may be nullptr
+  float2 *gH;           // may be nullptr
+  float2 *gy;           // may be nullptr
+  float *gnu;           // may be nullptr
+  float *gn0_part;      // [tasks] partial sums (workspace)
+  float *gn0;           // final scalar (may be nullptr)
+  int32_t W, B, U, C;
+  float n0, rho, es;
+  int32_t spw;
+  uint16_t off[EQ_MAX_C + 1];
+};
+
+// Host launchers (defined in the .hip files).
+hipError_t launch_forward(const FwdArgs &a, bool fd, int prec, hipStream_t s);
+hipError_t launch_fp64_resolve(const FwdArgs &a, bool fd, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
+hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
+int backward_tasks(int W, int U, int C, bool fd, int *spw);
+
+inline int ut_for(int U) { return U <= 16 ? 16 : 32; }
+inline int fd_spw(int UT, int C) {
+  const int nsys = 64 / UT;
+  return C >= nsys ? 1 : nsys / C;
+}
+
+}  // namespace dbpeq

@@ -1,0 +1,451 @@
+// Device building blocks of the equaliser kernels (gfx950, wave64).
+//
+// Work decomposition.  A wave owns a "round" of NSYS = 64/UT small systems
+// (UT = 16 or 32 is the padded user count).  Two layouts are used:
+//
+//  * streaming layout (Gram + matched filter): lane l covers column
+//    col = l % UT of H and row offset g = l / UT.  One load step reads
+//    RPS = 64/UT consecutive rows of H (RPS*U*8 contiguous bytes) with one
+//    8-byte load per lane.  The loaded value is at the same time the A and B
+//    operand of an MFMA whose K index runs over rows, so H_c^H H_c needs no
+//    LDS staging: FP32 MFMA consumes one load step per instruction
+//    (16x16x4 / 32x32x2), BF16 MFMA eight (16x16x32 / 32x32x16).
+//
+//  * solve layout: lane l works on system s = l / UT, row / column
+//    i = l % UT.  The Cholesky factor is held by rows (lane i owns row i of
+//    L), the inverse factor X = L^{-1} by columns (lane u owns column u), so
+//    diag(A^{-1})_u = sum_j |X_ju|^2 and z = X^H (L^{-1} m) need no
+//    cross-lane reduction.  Values move between lanes of a group by
+//    broadcasting one lane (DPP row broadcast or v_readlane).
+#pragma once
+#include <utility>
+
+#include "eq_common.h"
+
+namespace dbpeq {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- compile-time loops
+template <int... Is, class F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, F &&f) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+  sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// ---------------------------------------------------------------- cross-lane primitives
+// DPP controls (GCN/CDNA data-parallel primitives).
+constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_MIRROR = 0x140;    // lane i <-> 15 - i inside a row of 16
+constexpr int DPP_ROW_HMIRROR = 0x141;   // lane i <-> 7 - i inside half rows
+constexpr int DPP_ROW_NEWBCAST = 0x150;  // + k: lane k of each row to the whole row
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Value of lane K of this lane's group of UT lanes.
+template <int UT, int K>
+__device__ __forceinline__ float gbcast(float v) {
+#ifndef EQ_NO_DPP
+  if constexpr (UT == 16) {
+    return dpp<DPP_ROW_NEWBCAST + K>(v);
+  } else
+#endif
+  {
+    // one v_readlane per group, then select by group
+    if constexpr (UT == 16) {
+      const float v0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), K));
+      const float v1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 + K));
+      const float v2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + K));
+      const float v3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48 + K));
+      const int g = lane_id() >> 4;
+      return g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : v3;
+    } else {
+      const float v0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), K));
+      const float v1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + K));
+      return lane_id() < 32 ? v0 : v1;
+    }
+  }
+}
+template <int UT, int K>
+__device__ __forceinline__ float2 gbcast2(float2 v) {
+  return make_float2(gbcast<UT, K>(v.x), gbcast<UT, K>(v.y));
+}
+
+// Sum over the 16 lanes of a DPP row; every lane receives the sum.
+__device__ __forceinline__ float row16_sum(float v) {
+#ifndef EQ_NO_DPP
+  v += dpp<DPP_QUAD_XOR1>(v);
+  v += dpp<DPP_QUAD_XOR2>(v);
+  v += dpp<DPP_ROW_HMIRROR>(v);
+  v += dpp<DPP_ROW_MIRROR>(v);
+  return v;
+#else
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  return v;
+#endif
+}
+
+// Sum / max / any over an aligned group of UT lanes; all lanes get the result.
+template <int UT>
+__device__ __forceinline__ float gsum(float v) {
+  v = row16_sum(v);
+  if constexpr (UT == 32) v += __shfl_xor(v, 16);
+  return v;
+}
+template <int UT>
+__device__ __forceinline__ float gmax(float v) {
+  v = fmaxf(v, __shfl_xor(v, 1));
+  v = fmaxf(v, __shfl_xor(v, 2));
+  v = fmaxf(v, __shfl_xor(v, 4));
+  v = fmaxf(v, __shfl_xor(v, 8));
+  if constexpr (UT == 32) v = fmaxf(v, __shfl_xor(v, 16));
+  return v;
+}
+template <int UT>
+__device__ __forceinline__ bool gany(bool p) {
+  const unsigned long long m = __ballot(p);
+  const int s = lane_id() / UT;
+  const unsigned long long gm = (UT == 64) ? ~0ull : ((1ull << UT) - 1ull) << (s * UT);
+  return (m & gm) != 0ull;
+}
+
+// Sum over the 64/UT lanes that share a column in the streaming layout.
+template <int UT>
+__device__ __forceinline__ float colsum(float v) {
+  if constexpr (UT == 16) v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// ---------------------------------------------------------------- MFMA wrappers
+template <int UT> struct Acc;
+template <> struct Acc<16> { f4 rr, ri, ii; };
+template <> struct Acc<32> { f16v rr, ri, ii; };
+
+__device__ __forceinline__ f4 mma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f16v mma32(float a, float b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f16v mma16(bf8 a, bf8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Position (i, j) of accumulator register r in lane l.
+template <int UT>
+__device__ __forceinline__ void acc_pos(int l, int r, int &i, int &j) {
+  if constexpr (UT == 16) {
+    i = 4 * (l >> 4) + r;
+    j = l & 15;
+  } else {
+    i = 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    j = l & 31;
+  }
+}
+
+template <int UT>
+__device__ __forceinline__ void acc_zero(Acc<UT> &a) {
+  constexpr int NR = UT == 16 ? 4 : 16;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { a.rr[r] = 0.f; a.ri[r] = 0.f; a.ii[r] = 0.f; }
+}
+
+// ---------------------------------------------------------------- Gram + matched filter
+// Accumulates over rows [r0, r1) of one system (row stride U):
+//   acc.rr = Hr^T Hr, acc.ri = Hr^T Hi, acc.ii = Hi^T Hi  (real split of H^H H)
+//   mf (per lane, partial over its rows) = sum conj(H[row][col]) y[row]
+template <int UT, int PREC>
+__device__ __forceinline__ void gram_mf(const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
+                                        int U, int r0, int r1, Acc<UT> &acc, float2 &mf) {
+  constexpr int RPS = 64 / UT;
+  constexpr int RPB = 8 * RPS;
+  const int lane = lane_id();
+  const int col = lane % UT;
+  const int g = lane / UT;
+  const bool colok = col < U;
+  acc_zero<UT>(acc);
+  float mfx = 0.f, mfy = 0.f;
+  for (int rb = r0; rb < r1; rb += RPB) {
+    float2 h[8], yv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int row = rb + e * RPS + g;
+      const bool rv = row < r1;
+      h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
+      yv[e] = rv ? yw[row] : make_float2(0.f, 0.f);
+    }
+    if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        acc.rr = mma32(h[e].x, h[e].x, acc.rr);
+        acc.ri = mma32(h[e].x, h[e].y, acc.ri);
+        acc.ii = mma32(h[e].y, h[e].y, acc.ii);
+      }
+    } else if constexpr (PREC == PREC_BF16) {
+      bf8 re, im;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        re[e] = (__bf16)h[e].x;
+        im[e] = (__bf16)h[e].y;
+      }
+      acc.rr = mma16(re, re, acc.rr);
+      acc.ri = mma16(re, im, acc.ri);
+      acc.ii = mma16(im, im, acc.ii);
+    } else {
+      bf8 rh, rl, ih, il;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        rh[e] = (__bf16)h[e].x;
+        rl[e] = (__bf16)(h[e].x - (float)rh[e]);
+        ih[e] = (__bf16)h[e].y;
+        il[e] = (__bf16)(h[e].y - (float)ih[e]);
+      }
+      acc.rr = mma16(rh, rl, acc.rr);
+      acc.rr = mma16(rl, rh, acc.rr);
+      acc.rr = mma16(rh, rh, acc.rr);
+      acc.ri = mma16(rh, il, acc.ri);
+      acc.ri = mma16(rl, ih, acc.ri);
+      acc.ri = mma16(rh, ih, acc.ri);
+      acc.ii = mma16(ih, il, acc.ii);
+      acc.ii = mma16(il, ih, acc.ii);
+      acc.ii = mma16(ih, ih, acc.ii);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      // conj(h) * y
+      mfx += h[e].x * yv[e].x + h[e].y * yv[e].y;
+      mfy += h[e].x * yv[e].y - h[e].y * yv[e].x;
+    }
+  }
+  mf = make_float2(colsum<UT>(mfx), colsum<UT>(mfy));
+}
+
+// Residual pass of the refinement step for one system: with z broadcast so
+// that lane l holds z[col], accumulates n = H^H (y - H z) over rows [r0, r1).
+// Returns n[col] (valid in every lane).
+template <int UT>
+__device__ __forceinline__ float2 residual_mf(const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
+                                              int U, int r0, int r1, float2 zc) {
+  constexpr int RPS = 64 / UT;
+  constexpr int RPB = 8 * RPS;
+  const int lane = lane_id();
+  const int col = lane % UT;
+  const int g = lane / UT;
+  const bool colok = col < U;
+  float nx = 0.f, ny = 0.f;
+  for (int rb = r0; rb < r1; rb += RPB) {
+    float2 h[8], yv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int row = rb + e * RPS + g;
+      const bool rv = row < r1;
+      h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
+      yv[e] = rv ? yw[row] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      // (H z)_row = sum over the UT lanes of this row of h * z
+      const float px = gsum<UT>(h[e].x * zc.x - h[e].y * zc.y);
+      const float py = gsum<UT>(h[e].x * zc.y + h[e].y * zc.x);
+      const float rx = yv[e].x - px;
+      const float ry = yv[e].y - py;
+      nx += h[e].x * rx + h[e].y * ry;
+      ny += h[e].x * ry - h[e].y * rx;
+    }
+  }
+  return make_float2(colsum<UT>(nx), colsum<UT>(ny));
+}
+
+// Writes G + rho I of one system from the MFMA accumulators into LDS
+// (full Hermitian matrix, row stride UT + 1):
+//   Re G = Hr^T Hr + Hi^T Hi,   Im G[i][j] = (Hr^T Hi)[i][j] - (Hr^T Hi)[j][i].
+template <int UT>
+__device__ __forceinline__ void store_gram(float2 (*As)[UT + 1], const Acc<UT> &acc, float rho) {
+  constexpr int NR = UT == 16 ? 4 : 16;
+  const int lane = lane_id();
+  sfor<NR>([&](auto R) {
+    constexpr int r = R;
+    int i, j;
+    acc_pos<UT>(lane, r, i, j);
+    As[i][j] = make_float2(0.f, acc.ri[r]);
+  });
+  __syncthreads();
+  float im[NR];
+  sfor<NR>([&](auto R) {
+    constexpr int r = R;
+    int i, j;
+    acc_pos<UT>(lane, r, i, j);
+    im[r] = acc.ri[r] - As[j][i].y;
+  });
+  __syncthreads();
+  sfor<NR>([&](auto R) {
+    constexpr int r = R;
+    int i, j;
+    acc_pos<UT>(lane, r, i, j);
+    As[i][j] = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? rho : 0.f), im[r]);
+  });
+}
+
+template <int UT>
+__device__ __forceinline__ void store_identity(float2 (*As)[UT + 1]) {
+  for (int idx = lane_id(); idx < UT * UT; idx += 64) {
+    const int i = idx / UT, j = idx % UT;
+    As[i][j] = make_float2(i == j ? 1.f : 0.f, 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- factor / solves
+// Keeps the scheduler from hoisting the broadcasts of later pivot steps above
+// the current one (which would keep hundreds of values live at once).
+__device__ __forceinline__ void step_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Hides a register's value from common-subexpression elimination: the
+// inverse broadcasts the same (lane, register) pairs as the factorisation,
+// and reusing those would keep every broadcast of the factorisation live.
+__device__ __forceinline__ void opaque(float2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+
+template <int UT>
+struct Factor {
+  float2 a[UT];   // row i of L (entries j <= i), lane i of the group
+  float2 x[UT];   // column i of X = L^{-1}
+  float dinv;     // 1 / L_ii of this lane's row
+};
+
+// Right-looking Cholesky A = L L^H of the row held by each lane.
+// Returns 0, or j+1 for the first pivot j that is not positive (or NaN).
+template <int UT>
+__device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
+  int fail = 0;
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    const float ajj = gbcast<UT, j>(f.a[j].x);
+    if (!(ajj > 0.f) && fail == 0) fail = j + 1;
+    const float ljj = sqrtf(ajj);
+    const float inv = 1.0f / ljj;
+    if (i == j) f.dinv = inv;
+    float2 lij = make_float2(f.a[j].x * inv, f.a[j].y * inv);
+    if (i == j) lij = make_float2(ljj, 0.f);
+    if (i < j) lij = make_float2(0.f, 0.f);
+    f.a[j] = lij;
+    const float2 lm = (i > j) ? lij : make_float2(0.f, 0.f);
+    sfor<UT>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (k > j) {
+        const float2 lkj = gbcast2<UT, k>(lij);
+        // a_ik -= l_ij * conj(l_kj)
+        f.a[k].x -= lm.x * lkj.x + lm.y * lkj.y;
+        f.a[k].y -= lm.y * lkj.x - lm.x * lkj.y;
+      }
+    });
+    step_fence();
+  });
+  return fail;
+}
+
+// Lane u computes column u of X = L^{-1}:
+//   X_ju = (delta_ju - sum_{k<j} L_jk X_ku) / L_jj.
+// Row j of L is broadcast from lane j.  Each step's broadcast sources are
+// tied to the previous step's result, so the compiler neither hoists all
+// broadcasts to the top (hundreds of live values) nor merges them with the
+// identical broadcasts of the factorisation.
+template <int UT>
+__device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
+  float dep = 0.f;
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    float ax = (u == j) ? 1.f : 0.f, ay = 0.f;
+    sfor<UT>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (k < j) {
+        float2 src = f.a[k];
+        asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
+        const float2 ljk = gbcast2<UT, j>(src);
+        ax -= ljk.x * f.x[k].x - ljk.y * f.x[k].y;
+        ay -= ljk.x * f.x[k].y + ljk.y * f.x[k].x;
+      }
+    });
+    const float invj = gbcast<UT, j>(f.dinv);
+    f.x[j] = make_float2(ax * invj, ay * invj);
+    dep = f.x[j].x;
+    step_fence();
+  });
+}
+
+// t = L^{-1} b by forward substitution; lane i holds b_i on entry, t_i on exit.
+template <int UT>
+__device__ __forceinline__ float2 fwd_subst(const Factor<UT> &f, int i, float2 b) {
+  float2 t = b;
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    if (i == j) { t.x *= f.dinv; t.y *= f.dinv; }
+    const float2 tj = gbcast2<UT, j>(t);
+    if (i > j) {
+      t.x -= f.a[j].x * tj.x - f.a[j].y * tj.y;
+      t.y -= f.a[j].x * tj.y + f.a[j].y * tj.x;
+    }
+  });
+  return t;
+}
+
+// (X^H t)_u = sum_j conj(X_ju) t_j for lane u.
+template <int UT>
+__device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
+  float rx = 0.f, ry = 0.f;
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    const float2 tj = gbcast2<UT, j>(t);
+    rx += f.x[j].x * tj.x + f.x[j].y * tj.y;
+    ry += f.x[j].x * tj.y - f.x[j].y * tj.x;
+  });
+  return make_float2(rx, ry);
+}
+
+// Factorises A (rows in f.a) and solves A z = m: returns z_u at lane u,
+// fills f.x (columns of L^{-1}) and sets `fail` (0 or first bad pivot + 1).
+// The forward substitution runs before the inverse so the two independent
+// chains are not interleaved by the compiler.
+template <int UT>
+__device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail) {
+  fail = cholesky<UT>(f, i);
+  const float2 t = fwd_subst<UT>(f, i, m);
+  asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));
+  inverse_columns<UT>(f, i);
+  return apply_xh<UT>(f, t);
+}
+
+// A^{-1} b for lane-distributed b (lane i holds b_i); result at lane u.
+template <int UT>
+__device__ __forceinline__ float2 solve(const Factor<UT> &f, int i, float2 b) {
+  return apply_xh<UT>(f, fwd_subst<UT>(f, i, b));
+}
+
+// [A^{-1}]_uu for lane u.
+template <int UT>
+__device__ __forceinline__ float inv_diag(const Factor<UT> &f) {
+  float d = 0.f;
+#pragma unroll
+  for (int j = 0; j < UT; ++j) d += f.x[j].x * f.x[j].x + f.x[j].y * f.x[j].y;
+  return d;
+}
+
+__device__ __forceinline__ bool finite2(float2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+}  // namespace dbpeq

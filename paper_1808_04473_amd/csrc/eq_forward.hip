@@ -1,0 +1,301 @@
+// Forward kernels: fused Gram + matched filter + fusion + L-MMSE solve.
+//
+// PD (Section II-C, Section III-A): a wave equalises NSYS subcarriers.  The
+// adder tree of eq. (fullMRC) is the MFMA accumulator itself: the row blocks
+// of all clusters are accumulated into one G and one y^MRC, so the per-cluster
+// statistics are summed on chip and never leave the wave.
+//
+// FD (Section II-D, Section IV): a wave equalises all clusters of `spw`
+// subcarriers, NSYS local systems per round; after each round the local
+// estimates and variances go through LDS to the lanes that hold the fusion
+// sums of eq. (fusionrule) with the weights of Lemma 1 (eq. (opt_fusion)).
+//
+// The precision forms differ only in the Gram product (FP32 MFMA, BF16 MFMA,
+// or three BF16 MFMA products of split operands) and, for the BF16 forms, one
+// refinement step z += A^{-1} (H^H (y - H z) - rho z) with the FP32 residual.
+// Systems whose condition estimate ||A||_1 * trace(A^{-1}) exceeds
+// EQ_COND_LIMIT, or whose pivot failed, are queued for an FP64 re-solve.
+#include "eq_device.h"
+
+#ifndef EQ_WAVES_PER_EU
+#define EQ_WAVES_PER_EU 4
+#endif
+
+namespace dbpeq {
+
+template <int UT>
+struct Smem {
+  static constexpr int NSYS = 64 / UT;
+  float2 A[NSYS][UT][UT + 1];
+  float2 M[NSYS][UT];
+  float4 F[NSYS][UT];
+  int routed[NSYS];
+};
+
+// Queue subcarrier w for the FP64 re-solve (one lane calls this).
+__device__ __forceinline__ void enqueue_fp64(const FwdArgs &a, int w) {
+  const int pos = atomicAdd(a.fb_count, 1);
+  a.fb_list[pos] = w;
+}
+
+template <int UT, int PREC>
+__device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm) {
+  constexpr int NSYS = 64 / UT;
+  const int lane = lane_id();
+  const int sme = lane / UT;
+  const int i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+
+  // ---- Gram + matched filter of each subcarrier of the round
+  for (int s = 0; s < NSYS; ++s) {
+    const int w = task * NSYS + s;
+    if (w < a.W) {
+      Acc<UT> acc;
+      float2 mf;
+      gram_mf<UT, PREC>(a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, 0, a.B, acc, mf);
+      store_gram<UT>(sm.A[s], acc, a.rho);
+      if (lane < UT) sm.M[s][lane] = mf;
+    } else {
+      store_identity<UT>(sm.A[s]);
+      if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+
+  // ---- factor and solve: group sme, row/column i
+  const int w = task * NSYS + sme;
+  const bool live = w < a.W;
+  Factor<UT> f;
+  bool bad = false;
+  float rowsum = 0.f;
+#pragma unroll
+  for (int k = 0; k < UT; ++k) {
+    f.a[k] = sm.A[sme][i][k];
+    bad |= !finite2(f.a[k]);
+    rowsum += sqrtf(f.a[k].x * f.a[k].x + f.a[k].y * f.a[k].y);
+  }
+  const float2 m = sm.M[sme][i];
+  bad |= !finite2(m);
+  bad = gany<UT>(bad);
+  const float norm1 = gmax<UT>(i < a.U ? rowsum : 0.f);
+  int fail;
+  float2 z = factor_solve<UT>(f, i, m, fail);
+  const float d = inv_diag<UT>(f);
+
+  if constexpr (PREC != PREC_FP32) {
+    // ---- one refinement step with the FP32 residual y - H z
+    __syncthreads();
+    sm.M[sme][i] = z;
+    __syncthreads();
+    for (int s = 0; s < NSYS; ++s) {
+      const int ws = task * NSYS + s;
+      if (ws < a.W) {
+        const float2 zc = sm.M[s][lane % UT];
+        float2 n = residual_mf<UT>(a.H + (size_t)ws * HB, a.y + (size_t)ws * a.B, a.U, 0, a.B, zc);
+        n.x -= a.rho * zc.x;
+        n.y -= a.rho * zc.y;
+        __syncthreads();
+        if (lane < UT) sm.F[s][lane] = make_float4(n.x, n.y, 0.f, 0.f);
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    const float4 nv = sm.F[sme][i];
+    const float2 dz = solve<UT>(f, i, make_float2(nv.x, nv.y));
+    if (live) { z.x += dz.x; z.y += dz.y; }
+  }
+
+  const float kappa = norm1 * gsum<UT>(i < a.U ? d : 0.f);
+  const bool routed = live && !bad && (fail != 0 || !(kappa <= EQ_COND_LIMIT));
+  if (live) {
+    if (i < a.U) {
+      const float nanv = __int_as_float(0x7fc00000);
+      a.z[(size_t)w * a.U + i] = bad ? make_float2(nanv, nanv) : z;
+      if (a.s2) a.s2[(size_t)w * a.U + i] = bad ? nanv : a.n0 * d;
+    }
+    if (i == 0) {
+      if (a.info) a.info[w] = (bad ? -1 : fail) | (routed ? EQ_INFO_FP64 : 0);
+      if (routed) enqueue_fp64(a, w);
+    }
+  }
+}
+
+template <int UT, int PREC>
+__device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm) {
+  constexpr int NSYS = 64 / UT;
+  const int lane = lane_id();
+  const int sme = lane / UT;
+  const int i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+  const int C = a.C;
+  const int w0 = task * a.spw;
+  const int ntot = a.spw * C;
+  const bool user_nu = a.nu != nullptr;
+  const float nanv = __int_as_float(0x7fc00000);
+
+  // fusion sums held by lane (wl = lane / UT, u = lane % UT)
+  const int wlf = lane / UT;
+  float sw = 0.f, szx = 0.f, szy = 0.f, sv = 0.f;
+  if (lane < NSYS) sm.routed[lane] = 0;
+
+  for (int base = 0; base < ntot; base += NSYS) {
+    // ---- local Gram + MRC of the clusters of this round
+    for (int s = 0; s < NSYS; ++s) {
+      const int idx = base + s;
+      const int wl = idx / C, c = idx - (idx / C) * C;
+      const int w = w0 + wl;
+      if (idx < ntot && w < a.W) {
+        Acc<UT> acc;
+        float2 mf;
+        gram_mf<UT, PREC>(a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, a.off[c], a.off[c + 1], acc, mf);
+        store_gram<UT>(sm.A[s], acc, a.rho);
+        if (lane < UT) sm.M[s][lane] = mf;
+      } else {
+        store_identity<UT>(sm.A[s]);
+        if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
+      }
+    }
+    __syncthreads();
+
+    // ---- local L-MMSE of cluster (wl, c) by group sme
+    const int idx = base + sme;
+    const int wl = idx / C, c = idx - (idx / C) * C;
+    const int w = w0 + wl;
+    const bool live = idx < ntot && w < a.W;
+    Factor<UT> f;
+    bool bad = false;
+    float rowsum = 0.f;
+#pragma unroll
+    for (int k = 0; k < UT; ++k) {
+      f.a[k] = sm.A[sme][i][k];
+      bad |= !finite2(f.a[k]);
+      rowsum += sqrtf(f.a[k].x * f.a[k].x + f.a[k].y * f.a[k].y);
+    }
+    const float2 m = sm.M[sme][i];
+    bad |= !finite2(m);
+    bad = gany<UT>(bad);
+    const float norm1 = gmax<UT>(i < a.U ? rowsum : 0.f);
+    int fail;
+    float2 z = factor_solve<UT>(f, i, m, fail);
+    const float d = inv_diag<UT>(f);
+
+    if constexpr (PREC != PREC_FP32) {
+      __syncthreads();
+      sm.M[sme][i] = z;
+      __syncthreads();
+      for (int s = 0; s < NSYS; ++s) {
+        const int idx2 = base + s;
+        const int wl2 = idx2 / C, c2 = idx2 - (idx2 / C) * C;
+        const int w2 = w0 + wl2;
+        if (idx2 < ntot && w2 < a.W) {
+          const float2 zc = sm.M[s][lane % UT];
+          float2 n = residual_mf<UT>(a.H + (size_t)w2 * HB, a.y + (size_t)w2 * a.B, a.U,
+                                     a.off[c2], a.off[c2 + 1], zc);
+          n.x -= a.rho * zc.x;
+          n.y -= a.rho * zc.y;
+          __syncthreads();
+          if (lane < UT) sm.F[s][lane] = make_float4(n.x, n.y, 0.f, 0.f);
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+      const float4 nv = sm.F[sme][i];
+      const float2 dz = solve<UT>(f, i, make_float2(nv.x, nv.y));
+      if (live) { z.x += dz.x; z.y += dz.y; }
+    }
+
+    const float kappa = norm1 * gsum<UT>(i < a.U ? d : 0.f);
+    const bool routed = live && !bad && (fail != 0 || !(kappa <= EQ_COND_LIMIT));
+    if (live && i == 0) {
+      if (a.info) a.info[(size_t)w * C + c] = (bad ? -1 : fail) | (routed ? EQ_INFO_FP64 : 0);
+      if (routed) sm.routed[wl] = 1;
+    }
+    const float s2c = a.n0 * d;
+    __syncthreads();
+    sm.F[sme][i] = live ? (bad ? make_float4(nanv, nanv, nanv, 1.f) : make_float4(z.x, z.y, s2c, 1.f))
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+
+    // ---- fusion: lane (wlf, u) adds the clusters of its subcarrier, in c order
+    if (wlf < a.spw && i < a.U) {
+      for (int s = 0; s < NSYS; ++s) {
+        const int idx3 = base + s;
+        if (idx3 >= ntot || idx3 / C != wlf) continue;
+        const float4 v = sm.F[s][i];
+        if (v.w == 0.f) continue;
+        if (user_nu) {
+          const int c3 = idx3 - wlf * C;
+          const float nu = a.nu[((size_t)(w0 + wlf) * C + c3) * a.U + i];
+          szx += nu * v.x;
+          szy += nu * v.y;
+          sv += nu * nu * v.z;
+        } else {
+          const float p = 1.0f / v.z;
+          sw += p;
+          szx += p * v.x;
+          szy += p * v.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const int w = w0 + wlf;
+  if (wlf < a.spw && w < a.W) {
+    if (i < a.U) {
+      float2 zo;
+      float so;
+      if (user_nu) {
+        zo = make_float2(szx, szy);
+        so = sv;
+      } else {
+        const float inv = 1.0f / sw;
+        zo = make_float2(szx * inv, szy * inv);
+        so = inv;
+      }
+      a.z[(size_t)w * a.U + i] = zo;
+      if (a.s2) a.s2[(size_t)w * a.U + i] = so;
+    }
+    if (i == 0 && sm.routed[wlf]) enqueue_fp64(a, w);
+  }
+}
+
+template <int UT, int PREC, bool FD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(EQ_WAVES_PER_EU, 8))) void eq_forward_kernel(const FwdArgs a) {
+  __shared__ Smem<UT> sm;
+  if constexpr (FD)
+    fd_task<UT, PREC>(a, blockIdx.x, sm);
+  else
+    pd_task<UT, PREC>(a, blockIdx.x, sm);
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+template <int UT, bool FD>
+static hipError_t launch_prec(const FwdArgs &a, int prec, hipStream_t s) {
+  const int nsys = 64 / UT;
+  const int tasks = FD ? (a.W + a.spw - 1) / a.spw : (a.W + nsys - 1) / nsys;
+  const dim3 grid(tasks), block(64);
+  switch (prec) {
+    case PREC_FP32: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_FP32, FD>), grid, block, 0, s, a); break;
+    case PREC_BF16: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_BF16, FD>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_BF16X3, FD>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs &a, bool fd, int prec, hipStream_t s) {
+  const int UT = ut_for(a.U);
+  if (UT == 16) return fd ? launch_prec<16, true>(a, prec, s) : launch_prec<16, false>(a, prec, s);
+  return fd ? launch_prec<32, true>(a, prec, s) : launch_prec<32, false>(a, prec, s);
+}
+
+}  // namespace dbpeq

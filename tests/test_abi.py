@@ -1,0 +1,122 @@
+"""The C ABI (no GPU needed): the library loads, exports every entry point the
+header declares, and rejects invalid arguments on the host before any HIP
+call (EQ_EINVAL / EQ_ENOTSUP / EQ_EWORKSPACE, no device side effects)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1808_04473_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dbpeq.h")
+
+EINVAL, ENOTSUP, EWORKSPACE = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(api.LIB_PATH):
+        pytest.skip("libdbpeq.so not built (run python -m paper_1808_04473_amd.build)")
+    return api.load_library()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(eq_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ("eq_pd", "eq_fd", "eq_pd_backward", "eq_fd_backward", "eq_plan_create",
+              "eq_plan_execute", "eq_plan_destroy", "eq_workspace_size", "eq_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == {s[0] for s in api.SIGNATURES}
+
+
+def test_abi_version_and_status_strings(lib):
+    assert lib.eq_abi_version() == 1
+    for st, txt in api.STATUS.items():
+        assert lib.eq_status_string(st).decode() == txt
+
+
+def _prob(W=4, B=8, U=2, off=(0, 4, 8), n0=0.1, es=1.0, prec=0):
+    return api.make_problem(W, B, U, list(off), n0, es, prec)
+
+
+# dummy, suitably aligned host addresses: validation must reject before any use
+FAKE = ctypes.create_string_buffer(1 << 16)
+A = (ctypes.addressof(FAKE) + 255) // 256 * 256
+
+
+def _call_pd(lib, prob, H=A, y=A, z=A, s2=A, info=A, ws=A, wsb=1 << 12):
+    return lib.eq_pd(ctypes.byref(prob), H, y, z, s2, info, ws, wsb, None)
+
+
+def _call_fd(lib, prob, nu=None, H=A, y=A, z=A, ws=A, wsb=1 << 12):
+    return lib.eq_fd(ctypes.byref(prob), H, y, nu, z, A, A, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(n0=0.0), EINVAL), (dict(n0=-1.0), EINVAL), (dict(n0=float("nan")), EINVAL),
+    (dict(n0=float("inf")), EINVAL), (dict(es=0.0), EINVAL), (dict(es=float("nan")), EINVAL),
+    (dict(off=(0, 4, 7)), EINVAL), (dict(off=(1, 4, 8)), EINVAL), (dict(off=(0, 4, 4, 8)), EINVAL),
+    (dict(off=(0, 5, 4, 8)), EINVAL), (dict(U=0), EINVAL), (dict(U=33), ENOTSUP),
+    (dict(W=-1), EINVAL), (dict(B=0, off=(0,)), EINVAL), (dict(prec=7), EINVAL),
+    (dict(prec=-1), EINVAL),
+])
+def test_invalid_problem_rejected(lib, kw, expect):
+    prob, _keep = _prob(**kw)
+    assert _call_pd(lib, prob) == expect
+    assert _call_fd(lib, prob) == expect
+    assert lib.eq_workspace_size(ctypes.byref(prob)) == 0
+
+
+def test_too_many_clusters(lib):
+    prob, _k = api.make_problem(1, 2000, 2, list(range(0, 2001)), 0.1)
+    assert _call_pd(lib, prob) == ENOTSUP
+    prob, _k = api.make_problem(1, 70000, 2, [0, 70000], 0.1)
+    assert _call_pd(lib, prob) == ENOTSUP
+
+
+def test_null_and_misaligned_pointers(lib):
+    prob, _k = _prob()
+    assert _call_pd(lib, prob, H=None) == EINVAL
+    assert _call_pd(lib, prob, y=None) == EINVAL
+    assert _call_pd(lib, prob, z=None) == EINVAL
+    assert _call_pd(lib, prob, H=A + 4) == EINVAL
+    assert _call_pd(lib, prob, z=A + 2) == EINVAL
+    assert _call_pd(lib, prob, s2=A + 2) == EINVAL
+    assert _call_fd(lib, prob, nu=A + 1) == EINVAL
+    assert lib.eq_pd(None, A, A, A, A, A, A, 4096, None) == EINVAL
+
+
+def test_workspace_checked(lib):
+    prob, _k = _prob(W=1000)
+    need = lib.eq_workspace_size(ctypes.byref(prob))
+    assert need >= 256 + 4 * 1000
+    assert _call_pd(lib, prob, ws=None) == EWORKSPACE
+    assert _call_pd(lib, prob, wsb=need - 1) == EWORKSPACE
+
+
+def test_zero_systems_is_a_noop(lib):
+    prob, _k = _prob(W=0)
+    # no HIP call happens for W = 0, so this is safe without a GPU
+    assert lib.eq_pd(ctypes.byref(prob), None, None, None, None, None, None, 0, None) == 0
+    assert lib.eq_fd(ctypes.byref(prob), None, None, None, None, None, None, None, 0, None) == 0
+
+
+def test_python_binding_refuses_cpu_tensors(lib):
+    import torch
+    H = torch.zeros((2, 4, 2), dtype=torch.complex64)
+    y = torch.zeros((2, 4), dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        api.eq_pd(H, y, 0.1, [0, 4])
