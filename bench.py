@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of decentralized feedforward L-MMSE equalisation on one MI355X.
+
+Workload: B = 256 antennas in C = 8 clusters of 32, U = 16 users, 16-QAM,
+SNR 10 dB, i.i.d. Rayleigh H; one step equalises F frames x 1200 subcarriers
+(default F = 32: 38,400 independent systems, 1.34 GB of H and y, so the
+inputs stream from HBM rather than from the 256 MB Infinity Cache).  The
+headline `value` is partially-decentralised (PD) L-MMSE in FP32; every other
+form (FD fusion, BF16 / split-BF16 MFMA Gram with refinement) is timed the
+same way under "variants".  Inputs are resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+B, C, U, W_FRAME, SNR_DB = 256, 8, 16, 1200, 10.0
+HBM_PEAK_GBS = 8000.0
+CPU_SAMPLE_DEFAULT = 38400
+
+
+def bytes_per_system(B=B, U=U):
+    """Algorithmic HBM bytes of one system: read H and y once, write z and sigma2."""
+    return B * U * 8 + B * 8 + U * 8 + U * 4
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1808_04473_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(variant):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    e = t.get(variant)
+    if not e or e.get("source_sha") != kernel_source_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def make_inputs(frames):
+    from paper_1808_04473_amd import synth
+    Hs, ys = [], []
+    n0 = None
+    for f in range(frames):
+        b = synth.config_batch(2, SNR_DB, frame=f)
+        Hs.append(b.H)
+        ys.append(b.y)
+        n0 = b.n0
+        off = b.cluster_off
+    return np.concatenate(Hs), np.concatenate(ys), n0, off
+
+
+def cpu_baseline(H, y, n0, off, nsys):
+    """The FP64 oracle (as it stands) on the first `nsys` systems."""
+    import oracle
+    t0, c0 = time.perf_counter(), time.process_time()
+    oracle.eq_pd(H[:nsys], y[:nsys], n0, off)
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    return {"value": nsys / wall, "unit": "subcarriers/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"PD L-MMSE (complex128 numpy) on the first {nsys} of the step's systems, "
+                      f"{wall:.1f} s wall, {cpu:.1f} s CPU"}
+
+
+VARIANTS = [("pd", "fp32"), ("pd", "bf16"), ("pd", "bf16x3"),
+            ("fd", "fp32"), ("fd", "bf16"), ("fd", "bf16x3")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=32)
+    ap.add_argument("--variants", default="all",
+                    help="comma list of mode:prec (e.g. pd:fp32,fd:bf16x3) or 'all'")
+    ap.add_argument("--cpu-sample", type=int, default=CPU_SAMPLE_DEFAULT)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (PMC scale reference)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one MI355X: the equaliser is data-parallel over subcarriers "
+              "and this build has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1808_04473_amd import api
+    api.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t_gen = time.perf_counter()
+    Hn, yn, n0, off = make_inputs(args.frames)
+    gen_s = time.perf_counter() - t_gen
+    W = Hn.shape[0]
+    H = torch.from_numpy(Hn).to(dev)
+    y = torch.from_numpy(yn).to(dev)
+    torch.cuda.synchronize()
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    variants = VARIANTS if args.variants == "all" else [tuple(v.split(":")) for v in args.variants.split(",")]
+    bps = bytes_per_system()
+    results = {}
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(W, size=min(256, W), replace=False))
+    for mode, prec in variants:
+        z = torch.empty((W, U), dtype=torch.complex64, device=dev)
+        s2 = torch.empty((W, U), dtype=torch.float32, device=dev)
+        info = torch.empty((W,) if mode == "pd" else (W, C), dtype=torch.int32, device=dev)
+        prob, _k = api.make_problem(W, B, U, off, n0, 1.0, prec)
+        ws = api.workspace(prob, dev)
+        fn = api.eq_pd if mode == "pd" else api.eq_fd
+
+        def step():
+            fn(H, y, n0, off, precision=prec, out=(z, s2, info), ws=ws)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            step()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms, per call on the stream
+        ms = wall * 1e3 / args.steps
+        r = {"ms_per_step": ms, "subcarriers_per_s": W / (ms * 1e-3),
+             "call_ms_median": float(np.median(per)), "call_ms_p10": float(np.percentile(per, 10)),
+             "call_ms_p90": float(np.percentile(per, 90)),
+             "alg_GBps": W * bps / (float(np.mean(per)) * 1e-3) / 1e9}
+        r["hbm_frac"] = r["alg_GBps"] / HBM_PEAK_GBS
+        r["fp64_routed"] = int(((info & (1 << 30)) != 0).any(dim=-1).sum().item()) if mode == "fd" \
+            else int(((info & (1 << 30)) != 0).sum().item())
+        if not args.no_parity:
+            import oracle
+            Hs, ys = Hn[sample], yn[sample]
+            if mode == "pd":
+                zr, sr = oracle.eq_pd(Hs, ys, n0, off)
+            else:
+                zr, sr = oracle.eq_fd(Hs, ys, n0, off)
+            zg = z[torch.from_numpy(sample).to(dev)].cpu().numpy()
+            sg = s2[torch.from_numpy(sample).to(dev)].cpu().numpy()
+            r["parity_max_rel_err_z"] = float(np.max(np.max(np.abs(zg - zr), -1) / np.max(np.abs(zr), -1)))
+            r["parity_max_sigma2_db"] = float(np.max(np.abs(10 * np.log10(sg / sr))))
+        results[f"{mode}_{prec}"] = r
+        print(f"# {mode} {prec}: {ms:.3f} ms/step, {r['subcarriers_per_s'] / 1e6:.2f} M subcarriers/s, "
+              f"{r['alg_GBps']:.0f} GB/s ({100 * r['hbm_frac']:.1f}% of HBM peak)", file=sys.stderr, flush=True)
+        del z, s2, info, ws
+
+    head_key = "pd_fp32" if "pd_fp32" in results else next(iter(results))
+    head = results[head_key]
+    launch_bytes = W * bps
+    traffic = load_traffic(head_key)
+    out = {
+        "metric": "equalized subcarriers/s @B=256,U=16,C=8: FP32 vs BF16-MFMA; % HBM roofline",
+        "value": head["subcarriers_per_s"],
+        "unit": "subcarriers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"PD L-MMSE, B={B} antennas in C={C} clusters of {B // C}, U={U}, "
+                               f"{args.frames} frames x {W_FRAME} subcarriers = {W} systems per step, "
+                               f"16-QAM, SNR {SNR_DB:g} dB, i.i.d. Rayleigh",
+                   "B": B, "C": C, "U": U, "systems_per_step": W, "form": head_key},
+        "roofline": {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["hbm_frac"],
+                     "traffic": traffic,
+                     "kernel": "eq_forward_kernel<16, FP32, PD> (+ queue reset and FP64 re-solve "
+                               "launches, included in the timed call)",
+                     "alg_bytes_per_launch": launch_bytes,
+                     "alg_bytes_per_system": bps},
+        "variants": results,
+        "input_generation_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(Hn, yn, n0, off, min(args.cpu_sample, W))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -126,23 +126,30 @@ def workspace(prob: EqProblem, device) -> torch.Tensor:
     return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
 
 
-def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False):
-    """Partially decentralised L-MMSE of W systems: (z [W][U] c64, sigma2 [W][U] f32)."""
+def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
+          ws=None):
+    """Partially decentralised L-MMSE of W systems: (z [W][U] c64, sigma2 [W][U] f32).
+
+    `out` = (z, sigma2, info) and `ws` (uint8 workspace) may be preallocated."""
     lib = load_library()
     H, y = _check_inputs(H, y)
     W, B, U = H.shape
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
-    z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
-    s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
-    info = torch.empty((W,), dtype=torch.int32, device=H.device)
-    ws = workspace(prob, H.device)
+    if out is None:
+        z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
+        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+        info = torch.empty((W,), dtype=torch.int32, device=H.device)
+    else:
+        z, s2, info = out
+    ws = workspace(prob, H.device) if ws is None else ws
     st = lib.eq_pd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_pd", st)
     return (z, s2, info) if return_info else (z, s2)
 
 
-def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False):
+def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
+          out=None, ws=None):
     """Fully decentralised L-MMSE; nu [W][C][U] float32 user weights or None (optimal)."""
     lib = load_library()
     H, y = _check_inputs(H, y)
@@ -153,10 +160,13 @@ def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=
         if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
             raise ValueError("nu must be float32 [W][C][U] on the same device")
         nu = nu.contiguous()
-    z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
-    s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
-    info = torch.empty((W, C), dtype=torch.int32, device=H.device)
-    ws = workspace(prob, H.device)
+    if out is None:
+        z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
+        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+        info = torch.empty((W, C), dtype=torch.int32, device=H.device)
+    else:
+        z, s2, info = out
+    ws = workspace(prob, H.device) if ws is None else ws
     st = lib.eq_fd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(nu), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_fd", st)
