@@ -172,9 +172,10 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *host_desc, int32_t nsys,
 eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypool,
                           eq_c32 *zpool, float *s2pool, int32_t *info, void *stream);
 
-/* Tile choice of the plan: per U class (0: U <= 16, 1: U <= 32) the tuned
-   persistent grid size in waves (out_waves[2]) and the total tasks. */
-eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_waves, int32_t *out_tasks);
+/* Launch shape of the plan: out_shape[0] = persistent workgroups (one
+   wave each), out_shape[1] = 1 if PD work items hold half a round of systems
+   (else a full round of 64/UT systems of equal U); *out_tasks = work items. */
+eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_shape, int32_t *out_tasks);
 
 eq_status eq_plan_destroy(eq_plan *plan);
 

@@ -171,3 +171,125 @@ def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_fd", st)
     return (z, s2, info) if return_info else (z, s2)
+
+
+def _bwd_workspace(prob: EqProblem, device) -> torch.Tensor:
+    lib = load_library()
+    n = lib.eq_backward_workspace_size(ctypes.byref(prob))
+    return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+
+
+def _grad_inputs(gz, gs, W, U, device):
+    if gz is not None:
+        if gz.dtype != torch.complex64 or tuple(gz.shape) != (W, U) or gz.device != device:
+            raise ValueError("gz must be complex64 [W][U] on the device")
+        gz = gz.contiguous()
+    if gs is not None:
+        if gs.dtype != torch.float32 or tuple(gs.shape) != (W, U) or gs.device != device:
+            raise ValueError("gs must be float32 [W][U] on the device")
+        gs = gs.contiguous()
+    return gz, gs
+
+
+def eq_pd_backward(H, y, n0, cluster_off, gz=None, gs=None, es=1.0):
+    """Adjoint of eq_pd: (grad_H [W][B][U], grad_y [W][B], grad_N0 0-dim float32)."""
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, "fp32")
+    gz, gs = _grad_inputs(gz, gs, W, U, H.device)
+    gH = torch.empty_like(H)
+    gy = torch.empty_like(y)
+    gn0 = torch.zeros((), dtype=torch.float32, device=H.device)
+    ws = _bwd_workspace(prob, H.device)
+    st = lib.eq_pd_backward(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(gz), _ptr(gs), _ptr(gH),
+                            _ptr(gy), _ptr(gn0), _ptr(ws), ws.numel(), _stream())
+    _check("eq_pd_backward", st)
+    return gH, gy, gn0
+
+
+def eq_fd_backward(H, y, n0, cluster_off, gz=None, gs=None, nu=None, es=1.0):
+    """Adjoint of eq_fd: (grad_H, grad_y, grad_N0, grad_nu or None)."""
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, "fp32")
+    gz, gs = _grad_inputs(gz, gs, W, U, H.device)
+    gnu = None
+    if nu is not None:
+        nu = nu.contiguous()
+        gnu = torch.empty_like(nu)
+    gH = torch.empty_like(H)
+    gy = torch.empty_like(y)
+    gn0 = torch.zeros((), dtype=torch.float32, device=H.device)
+    ws = _bwd_workspace(prob, H.device)
+    st = lib.eq_fd_backward(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(nu), _ptr(gz), _ptr(gs),
+                            _ptr(gH), _ptr(gy), _ptr(gn0), _ptr(gnu), _ptr(ws), ws.numel(), _stream())
+    _check("eq_fd_backward", st)
+    return gH, gy, gn0, gnu
+
+
+class Plan:
+    """A ragged batch of independent systems (eq_plan_* of the C ABI).
+
+    desc arrays (numpy, length nsys): B, U, C, n0, h_off, y_off, z_off,
+    clus_first; cluster_sizes (int32) holds every system's cluster sizes.
+    Offsets are in complex elements of the pools passed to execute()."""
+
+    def __init__(self, B, U, C, n0, h_off, y_off, z_off, clus_first, cluster_sizes, fd=False,
+                 precision="fp32", es=1.0, tune_cache=None):
+        lib = load_library()
+        n = len(B)
+        self.nsys = n
+        self.fd = bool(fd)
+        desc = (EqSys * n)()
+        for k in range(n):
+            desc[k] = EqSys(int(h_off[k]), int(y_off[k]), int(z_off[k]), int(B[k]), int(U[k]), int(C[k]),
+                            int(clus_first[k]), float(n0[k]), 0)
+        sizes = np.ascontiguousarray(np.asarray(cluster_sizes, dtype=np.int32))
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = c_void_p()
+        st = lib.eq_plan_create(ctypes.byref(h), desc, n, sizes.ctypes.data_as(POINTER(c_int32)),
+                                len(sizes), int(bool(fd)), prec, float(es),
+                                None if tune_cache is None else str(tune_cache).encode())
+        _check("eq_plan_create", st)
+        self._h = h
+        self._lib = lib
+        self.nz = int(max(np.asarray(z_off, np.int64) + np.asarray(U, np.int64)))
+
+    @classmethod
+    def from_ragged(cls, rb, fd=False, precision="fp32", tune_cache=None):
+        return cls(rb.B, rb.U, rb.C, rb.n0, rb.h_off, rb.y_off, rb.z_off, rb.clus_first,
+                   rb.cluster_sizes, fd=fd, precision=precision, es=rb.es, tune_cache=tune_cache)
+
+    def execute(self, Hpool, ypool, out=None):
+        for t in (Hpool, ypool):
+            if t.device.type != "cuda" or t.dtype != torch.complex64 or not t.is_contiguous():
+                raise ValueError("pools must be contiguous complex64 device tensors")
+        if out is None:
+            z = torch.empty(self.nz, dtype=torch.complex64, device=Hpool.device)
+            s2 = torch.empty(self.nz, dtype=torch.float32, device=Hpool.device)
+            info = torch.empty(self.nsys, dtype=torch.int32, device=Hpool.device)
+        else:
+            z, s2, info = out
+        st = self._lib.eq_plan_execute(self._h, _ptr(Hpool), _ptr(ypool), _ptr(z), _ptr(s2), _ptr(info),
+                                       _stream())
+        _check("eq_plan_execute", st)
+        return z, s2, info
+
+    def describe(self):
+        shape = (c_int32 * 2)()
+        nt = c_int32()
+        _check("eq_plan_describe", self._lib.eq_plan_describe(self._h, shape, ctypes.byref(nt)))
+        return {"grid": shape[0], "half_items": shape[1], "tasks": nt.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.eq_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -75,9 +75,77 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   return EQ_OK;
 }
 
+size_t bwd_ws_bytes(const eq_problem *p) {
+  int spw;
+  const int nt = backward_tasks(p->W > 0 ? p->W : 1, p->U, p->C, true, &spw);
+  const int nt_pd = backward_tasks(p->W > 0 ? p->W : 1, p->U, p->C, false, &spw);
+  const size_t parts = (size_t)(((nt > nt_pd ? nt : nt_pd) + 63) / 64) * 64 * sizeof(float);
+  const size_t fwd = (size_t)(p->W > 0 ? p->W : 1) * p->C * p->U * 16;
+  return parts + fwd;
+}
+
+eq_status backward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                   const eq_c32 *gz, const float *gs, eq_c32 *gH, eq_c32 *gy, float *gn0, float *gnu,
+                   void *ws, size_t ws_bytes, void *stream) {
+  eq_status st = check_problem(p);
+  if (st != EQ_OK) return st;
+  if (!fd && (nu || gnu)) return EQ_EINVAL;
+  if (fd && gnu && !nu) return EQ_EINVAL;
+  if (p->W == 0) return EQ_OK;
+  if (!H || !y) return EQ_EINVAL;
+  if (!aligned(H, 8) || !aligned(y, 8) || (gz && !aligned(gz, 8)) || (gH && !aligned(gH, 8)) ||
+      (gy && !aligned(gy, 8)))
+    return EQ_EINVAL;
+  if ((gs && !aligned(gs, 4)) || (gn0 && !aligned(gn0, 4)) || (nu && !aligned(nu, 4)) ||
+      (gnu && !aligned(gnu, 4)))
+    return EQ_EINVAL;
+  if (!ws || ws_bytes < bwd_ws_bytes(p) || !aligned(ws, 256)) return EQ_EWORKSPACE;
+  BwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.W = p->W;
+  a.B = p->B;
+  a.U = p->U;
+  a.C = p->C;
+  a.n0 = p->n0;
+  a.es = p->es;
+  a.rho = p->n0 / p->es;
+  for (int c = 0; c <= p->C; ++c) a.off[c] = (uint16_t)p->cluster_off[c];
+  const int ntasks = backward_tasks(p->W, p->U, p->C, fd, &a.spw);
+  a.H = reinterpret_cast<const float2 *>(H);
+  a.y = reinterpret_cast<const float2 *>(y);
+  a.nu = nu;
+  a.gz = reinterpret_cast<const float2 *>(gz);
+  a.gs = gs;
+  a.gH = reinterpret_cast<float2 *>(gH);
+  a.gy = reinterpret_cast<float2 *>(gy);
+  a.gnu = gnu;
+  a.gn0_part = reinterpret_cast<float *>(ws);
+  a.gn0 = gn0;
+  if (launch_backward(a, fd, ntasks, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return EQ_EHIP;
+  return EQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t eq_backward_workspace_size(const eq_problem *p) {
+  if (check_problem(p) != EQ_OK) return 0;
+  return bwd_ws_bytes(p);
+}
+
+eq_status eq_pd_backward(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, const eq_c32 *gz,
+                         const float *gs, eq_c32 *gH, eq_c32 *gy, float *gn0, void *ws, size_t ws_bytes,
+                         void *stream) {
+  return backward(p, false, H, y, nullptr, gz, gs, gH, gy, gn0, nullptr, ws, ws_bytes, stream);
+}
+
+eq_status eq_fd_backward(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                         const eq_c32 *gz, const float *gs, eq_c32 *gH, eq_c32 *gy, float *gn0,
+                         float *gnu, void *ws, size_t ws_bytes, void *stream) {
+  return backward(p, true, H, y, nu, gz, gs, gH, gy, gn0, gnu, ws, ws_bytes, stream);
+}
+
 
 int32_t eq_abi_version(void) { return EQ_ABI_VERSION; }
 

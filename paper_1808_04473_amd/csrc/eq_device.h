@@ -169,109 +169,184 @@ __device__ __forceinline__ void acc_zero(Acc<UT> &a) {
 }
 
 // ---------------------------------------------------------------- Gram + matched filter
-// Accumulates over rows [r0, r1) of one system (row stride U):
-//   acc.rr = Hr^T Hr, acc.ri = Hr^T Hi, acc.ii = Hi^T Hi  (real split of H^H H)
-//   mf (per lane, partial over its rows) = sum conj(H[row][col]) y[row]
-template <int UT, int PREC>
-__device__ __forceinline__ void gram_mf(const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
-                                        int U, int r0, int r1, Acc<UT> &acc, float2 &mf) {
+// One block = 8 load steps = 8 * (64/UT) rows of one system, in the
+// streaming layout (lane: column col, rows rb + e*RPS + g for e = 0..7).
+struct Blk {
+  float2 h[8];
+  float2 y[8];
+};
+
+template <int UT>
+__device__ __forceinline__ void load_blk(Blk &b, const float2 *__restrict__ Hw,
+                                         const float2 *__restrict__ yw, int U, int rb, int r1) {
   constexpr int RPS = 64 / UT;
-  constexpr int RPB = 8 * RPS;
   const int lane = lane_id();
   const int col = lane % UT;
   const int g = lane / UT;
   const bool colok = col < U;
-  acc_zero<UT>(acc);
-  float mfx = 0.f, mfy = 0.f;
-  for (int rb = r0; rb < r1; rb += RPB) {
-    float2 h[8], yv[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int row = rb + e * RPS + g;
-      const bool rv = row < r1;
-      h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
-      yv[e] = rv ? yw[row] : make_float2(0.f, 0.f);
-    }
-    if constexpr (PREC == PREC_FP32) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        acc.rr = mma32(h[e].x, h[e].x, acc.rr);
-        acc.ri = mma32(h[e].x, h[e].y, acc.ri);
-        acc.ii = mma32(h[e].y, h[e].y, acc.ii);
-      }
-    } else if constexpr (PREC == PREC_BF16) {
-      bf8 re, im;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        re[e] = (__bf16)h[e].x;
-        im[e] = (__bf16)h[e].y;
-      }
-      acc.rr = mma16(re, re, acc.rr);
-      acc.ri = mma16(re, im, acc.ri);
-      acc.ii = mma16(im, im, acc.ii);
-    } else {
-      bf8 rh, rl, ih, il;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        rh[e] = (__bf16)h[e].x;
-        rl[e] = (__bf16)(h[e].x - (float)rh[e]);
-        ih[e] = (__bf16)h[e].y;
-        il[e] = (__bf16)(h[e].y - (float)ih[e]);
-      }
-      acc.rr = mma16(rh, rl, acc.rr);
-      acc.rr = mma16(rl, rh, acc.rr);
-      acc.rr = mma16(rh, rh, acc.rr);
-      acc.ri = mma16(rh, il, acc.ri);
-      acc.ri = mma16(rl, ih, acc.ri);
-      acc.ri = mma16(rh, ih, acc.ri);
-      acc.ii = mma16(ih, il, acc.ii);
-      acc.ii = mma16(il, ih, acc.ii);
-      acc.ii = mma16(ih, ih, acc.ii);
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      // conj(h) * y
-      mfx += h[e].x * yv[e].x + h[e].y * yv[e].y;
-      mfy += h[e].x * yv[e].y - h[e].y * yv[e].x;
-    }
+  for (int e = 0; e < 8; ++e) {
+    const int row = rb + e * RPS + g;
+    const bool rv = row < r1;
+    b.h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
+    b.y[e] = rv ? yw[row] : make_float2(0.f, 0.f);
   }
-  mf = make_float2(colsum<UT>(mfx), colsum<UT>(mfy));
 }
 
-// Residual pass of the refinement step for one system: with z broadcast so
-// that lane l holds z[col], accumulates n = H^H (y - H z) over rows [r0, r1).
-// Returns n[col] (valid in every lane).
-template <int UT>
-__device__ __forceinline__ float2 residual_mf(const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
-                                              int U, int r0, int r1, float2 zc) {
-  constexpr int RPS = 64 / UT;
-  constexpr int RPB = 8 * RPS;
-  const int lane = lane_id();
-  const int col = lane % UT;
-  const int g = lane / UT;
-  const bool colok = col < U;
-  float nx = 0.f, ny = 0.f;
-  for (int rb = r0; rb < r1; rb += RPB) {
-    float2 h[8], yv[8];
+// acc += real split of the block's H^H H (rr = Hr^T Hr, ri = Hr^T Hi,
+// ii = Hi^T Hi); (mfx, mfy) += partial of sum conj(H[row][col]) y[row].
+template <int UT, int PREC>
+__device__ __forceinline__ void gram_blk(const Blk &b, Acc<UT> &acc, float &mfx, float &mfy) {
+  if constexpr (PREC == PREC_FP32) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int row = rb + e * RPS + g;
-      const bool rv = row < r1;
-      h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
-      yv[e] = rv ? yw[row] : make_float2(0.f, 0.f);
+      acc.rr = mma32(b.h[e].x, b.h[e].x, acc.rr);
+      acc.ri = mma32(b.h[e].x, b.h[e].y, acc.ri);
+      acc.ii = mma32(b.h[e].y, b.h[e].y, acc.ii);
     }
+  } else if constexpr (PREC == PREC_BF16) {
+    bf8 re, im;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      re[e] = (__bf16)b.h[e].x;
+      im[e] = (__bf16)b.h[e].y;
+    }
+    acc.rr = mma16(re, re, acc.rr);
+    acc.ri = mma16(re, im, acc.ri);
+    acc.ii = mma16(im, im, acc.ii);
+  } else {
+    bf8 rh, rl, ih, il;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      rh[e] = (__bf16)b.h[e].x;
+      rl[e] = (__bf16)(b.h[e].x - (float)rh[e]);
+      ih[e] = (__bf16)b.h[e].y;
+      il[e] = (__bf16)(b.h[e].y - (float)ih[e]);
+    }
+    acc.rr = mma16(rh, rl, acc.rr);
+    acc.rr = mma16(rl, rh, acc.rr);
+    acc.rr = mma16(rh, rh, acc.rr);
+    acc.ri = mma16(rh, il, acc.ri);
+    acc.ri = mma16(rl, ih, acc.ri);
+    acc.ri = mma16(rh, ih, acc.ri);
+    acc.ii = mma16(ih, il, acc.ii);
+    acc.ii = mma16(il, ih, acc.ii);
+    acc.ii = mma16(ih, ih, acc.ii);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    // conj(h) * y
+    mfx += b.h[e].x * b.y[e].x + b.h[e].y * b.y[e].y;
+    mfy += b.h[e].x * b.y[e].y - b.h[e].y * b.y[e].x;
+  }
+}
+
+// Streams the row blocks of `ns` systems back to back with the next block's
+// loads in flight while the current block is multiplied (the prefetch runs
+// across system boundaries).  seg(s, Hw, yw, r0, r1) describes system s;
+// after its last block, done(s, acc, mf) receives its Gram accumulators and
+// matched filter (mf reduced over the lanes of a column).
+template <int UT, int PREC, class Seg, class Done>
+__device__ __forceinline__ void gram_stream(int ns, int U, Seg seg, Done done) {
+  constexpr int RPB = 8 * (64 / UT);
+  if (ns <= 0) return;
+  const float2 *Hw, *yw;
+  int r0, r1;
+  seg(0, Hw, yw, r0, r1);
+  int s = 0, rb = r0;
+  Blk cur, nxt;
+  load_blk<UT>(cur, Hw, yw, U, rb, r1);
+  Acc<UT> acc;
+  acc_zero<UT>(acc);
+  float mfx = 0.f, mfy = 0.f;
+  while (true) {
+    const float2 *Hn = Hw, *yn = yw;
+    int sn = s, rbn = rb + RPB, r0n = r0, r1n = r1;
+    const bool last = rbn >= r1;
+    bool more = true;
+    if (last) {
+      sn = s + 1;
+      if (sn < ns) {
+        seg(sn, Hn, yn, r0n, r1n);
+        rbn = r0n;
+      } else {
+        more = false;
+      }
+    }
+    if (more) load_blk<UT>(nxt, Hn, yn, U, rbn, r1n);
+    gram_blk<UT, PREC>(cur, acc, mfx, mfy);
+    if (last) {
+      done(s, acc, make_float2(colsum<UT>(mfx), colsum<UT>(mfy)));
+      acc_zero<UT>(acc);
+      mfx = 0.f;
+      mfy = 0.f;
+    }
+    if (!more) break;
+    cur = nxt;
+    s = sn;
+    rb = rbn;
+    Hw = Hn;
+    yw = yn;
+    r0 = r0n;
+    r1 = r1n;
+  }
+}
+
+// Residual pass of the refinement step, streamed like gram_stream: for
+// system s (zc(s) gives z[col] of that system in every lane) accumulates
+// n = H^H (y - H z) and calls done(s, n) with n[col] valid in every lane.
+template <int UT, class Seg, class Zc, class Done>
+__device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, Done done) {
+  constexpr int RPB = 8 * (64 / UT);
+  if (ns <= 0) return;
+  const float2 *Hw, *yw;
+  int r0, r1;
+  seg(0, Hw, yw, r0, r1);
+  int s = 0, rb = r0;
+  Blk cur, nxt;
+  load_blk<UT>(cur, Hw, yw, U, rb, r1);
+  float2 zc = zcf(0);
+  float nx = 0.f, ny = 0.f;
+  while (true) {
+    const float2 *Hn = Hw, *yn = yw;
+    int sn = s, rbn = rb + RPB, r0n = r0, r1n = r1;
+    const bool last = rbn >= r1;
+    bool more = true;
+    if (last) {
+      sn = s + 1;
+      if (sn < ns) {
+        seg(sn, Hn, yn, r0n, r1n);
+        rbn = r0n;
+      } else {
+        more = false;
+      }
+    }
+    if (more) load_blk<UT>(nxt, Hn, yn, U, rbn, r1n);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       // (H z)_row = sum over the UT lanes of this row of h * z
-      const float px = gsum<UT>(h[e].x * zc.x - h[e].y * zc.y);
-      const float py = gsum<UT>(h[e].x * zc.y + h[e].y * zc.x);
-      const float rx = yv[e].x - px;
-      const float ry = yv[e].y - py;
-      nx += h[e].x * rx + h[e].y * ry;
-      ny += h[e].x * ry - h[e].y * rx;
+      const float px = gsum<UT>(cur.h[e].x * zc.x - cur.h[e].y * zc.y);
+      const float py = gsum<UT>(cur.h[e].x * zc.y + cur.h[e].y * zc.x);
+      const float rx = cur.y[e].x - px;
+      const float ry = cur.y[e].y - py;
+      nx += cur.h[e].x * rx + cur.h[e].y * ry;
+      ny += cur.h[e].x * ry - cur.h[e].y * rx;
     }
+    if (last) {
+      done(s, make_float2(colsum<UT>(nx), colsum<UT>(ny)));
+      nx = 0.f;
+      ny = 0.f;
+    }
+    if (!more) break;
+    cur = nxt;
+    s = sn;
+    rb = rbn;
+    Hw = Hn;
+    yw = yn;
+    r0 = r0n;
+    r1 = r1n;
+    if (last) zc = zcf(s);
   }
-  return make_float2(colsum<UT>(nx), colsum<UT>(ny));
 }
 
 // Writes G + rho I of one system from the MFMA accumulators into LDS

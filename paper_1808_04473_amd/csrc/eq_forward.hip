@@ -15,22 +15,13 @@
 // refinement step z += A^{-1} (H^H (y - H z) - rho z) with the FP32 residual.
 // Systems whose condition estimate ||A||_1 * trace(A^{-1}) exceeds
 // EQ_COND_LIMIT, or whose pivot failed, are queued for an FP64 re-solve.
-#include "eq_device.h"
+#include "eq_round.h"
 
 #ifndef EQ_WAVES_PER_EU
 #define EQ_WAVES_PER_EU 4
 #endif
 
 namespace dbpeq {
-
-template <int UT>
-struct Smem {
-  static constexpr int NSYS = 64 / UT;
-  float2 A[NSYS][UT][UT + 1];
-  float2 M[NSYS][UT];
-  float4 F[NSYS][UT];
-  int routed[NSYS];
-};
 
 // Queue subcarrier w for the FP64 re-solve (one lane calls this).
 __device__ __forceinline__ void enqueue_fp64(const FwdArgs &a, int w) {
@@ -45,76 +36,44 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm
   const int sme = lane / UT;
   const int i = lane % UT;
   const size_t HB = (size_t)a.B * a.U;
+  const int nvalid = min(NSYS, a.W - task * NSYS);
+  auto seg = [&](int s, const float2 *&Hw, const float2 *&yw, int &r0, int &r1) {
+    const size_t w = (size_t)task * NSYS + s;
+    Hw = a.H + w * HB;
+    yw = a.y + w * a.B;
+    r0 = 0;
+    r1 = a.B;
+  };
 
-  // ---- Gram + matched filter of each subcarrier of the round
-  for (int s = 0; s < NSYS; ++s) {
-    const int w = task * NSYS + s;
-    if (w < a.W) {
-      Acc<UT> acc;
-      float2 mf;
-      gram_mf<UT, PREC>(a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, 0, a.B, acc, mf);
-      store_gram<UT>(sm.A[s], acc, a.rho);
-      if (lane < UT) sm.M[s][lane] = mf;
-    } else {
-      store_identity<UT>(sm.A[s]);
-      if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
-    }
+  // ---- Gram + matched filter of the round's subcarriers (all clusters
+  //      accumulate into one G and one y^MRC: the adder tree of eq. (fullMRC))
+  gram_stream<UT, PREC>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+    store_gram<UT>(sm.A[s], acc, a.rho);
+    if (lane < UT) sm.M[s][lane] = mf;
+  });
+  for (int s = nvalid; s < NSYS; ++s) {
+    store_identity<UT>(sm.A[s]);
+    if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
   }
   __syncthreads();
 
   // ---- factor and solve: group sme, row/column i
   const int w = task * NSYS + sme;
-  const bool live = w < a.W;
-  Factor<UT> f;
-  bool bad = false;
-  float rowsum = 0.f;
-#pragma unroll
-  for (int k = 0; k < UT; ++k) {
-    f.a[k] = sm.A[sme][i][k];
-    bad |= !finite2(f.a[k]);
-    rowsum += sqrtf(f.a[k].x * f.a[k].x + f.a[k].y * f.a[k].y);
-  }
-  const float2 m = sm.M[sme][i];
-  bad |= !finite2(m);
-  bad = gany<UT>(bad);
-  const float norm1 = gmax<UT>(i < a.U ? rowsum : 0.f);
-  int fail;
-  float2 z = factor_solve<UT>(f, i, m, fail);
-  const float d = inv_diag<UT>(f);
+  const bool live = sme < nvalid;
+  LocalSolve<UT> r;
+  local_solve<UT>(r, sm, sme, i, a.U);
+  if constexpr (PREC != PREC_FP32) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
-  if constexpr (PREC != PREC_FP32) {
-    // ---- one refinement step with the FP32 residual y - H z
-    __syncthreads();
-    sm.M[sme][i] = z;
-    __syncthreads();
-    for (int s = 0; s < NSYS; ++s) {
-      const int ws = task * NSYS + s;
-      if (ws < a.W) {
-        const float2 zc = sm.M[s][lane % UT];
-        float2 n = residual_mf<UT>(a.H + (size_t)ws * HB, a.y + (size_t)ws * a.B, a.U, 0, a.B, zc);
-        n.x -= a.rho * zc.x;
-        n.y -= a.rho * zc.y;
-        __syncthreads();
-        if (lane < UT) sm.F[s][lane] = make_float4(n.x, n.y, 0.f, 0.f);
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-    const float4 nv = sm.F[sme][i];
-    const float2 dz = solve<UT>(f, i, make_float2(nv.x, nv.y));
-    if (live) { z.x += dz.x; z.y += dz.y; }
-  }
-
-  const float kappa = norm1 * gsum<UT>(i < a.U ? d : 0.f);
-  const bool routed = live && !bad && (fail != 0 || !(kappa <= EQ_COND_LIMIT));
+  const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
+  const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
   if (live) {
     if (i < a.U) {
       const float nanv = __int_as_float(0x7fc00000);
-      a.z[(size_t)w * a.U + i] = bad ? make_float2(nanv, nanv) : z;
-      if (a.s2) a.s2[(size_t)w * a.U + i] = bad ? nanv : a.n0 * d;
+      a.z[(size_t)w * a.U + i] = r.bad ? make_float2(nanv, nanv) : r.z;
+      if (a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d;
     }
     if (i == 0) {
-      if (a.info) a.info[w] = (bad ? -1 : fail) | (routed ? EQ_INFO_FP64 : 0);
+      if (a.info) a.info[w] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) enqueue_fp64(a, w);
     }
   }
@@ -129,7 +88,8 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
   const size_t HB = (size_t)a.B * a.U;
   const int C = a.C;
   const int w0 = task * a.spw;
-  const int ntot = a.spw * C;
+  // clusters of the subcarriers of this task that exist
+  const int ntot = min(a.spw, a.W - w0) * C;
   const bool user_nu = a.nu != nullptr;
   const float nanv = __int_as_float(0x7fc00000);
 
@@ -139,90 +99,54 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
   if (lane < NSYS) sm.routed[lane] = 0;
 
   for (int base = 0; base < ntot; base += NSYS) {
-    // ---- local Gram + MRC of the clusters of this round
-    for (int s = 0; s < NSYS; ++s) {
+    const int nvalid = min(NSYS, ntot - base);
+    auto seg = [&](int s, const float2 *&Hw, const float2 *&yw, int &r0, int &r1) {
       const int idx = base + s;
-      const int wl = idx / C, c = idx - (idx / C) * C;
-      const int w = w0 + wl;
-      if (idx < ntot && w < a.W) {
-        Acc<UT> acc;
-        float2 mf;
-        gram_mf<UT, PREC>(a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, a.off[c], a.off[c + 1], acc, mf);
-        store_gram<UT>(sm.A[s], acc, a.rho);
-        if (lane < UT) sm.M[s][lane] = mf;
-      } else {
-        store_identity<UT>(sm.A[s]);
-        if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
-      }
+      const int wl = idx / C, c = idx - wl * C;
+      const size_t w = (size_t)(w0 + wl);
+      Hw = a.H + w * HB;
+      yw = a.y + w * a.B;
+      r0 = a.off[c];
+      r1 = a.off[c + 1];
+    };
+    // ---- local Gram + MRC of the clusters of this round
+    gram_stream<UT, PREC>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+      store_gram<UT>(sm.A[s], acc, a.rho);
+      if (lane < UT) sm.M[s][lane] = mf;
+    });
+    for (int s = nvalid; s < NSYS; ++s) {
+      store_identity<UT>(sm.A[s]);
+      if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
     }
     __syncthreads();
 
     // ---- local L-MMSE of cluster (wl, c) by group sme
     const int idx = base + sme;
-    const int wl = idx / C, c = idx - (idx / C) * C;
+    const int wl = idx / C, c = idx - wl * C;
     const int w = w0 + wl;
-    const bool live = idx < ntot && w < a.W;
-    Factor<UT> f;
-    bool bad = false;
-    float rowsum = 0.f;
-#pragma unroll
-    for (int k = 0; k < UT; ++k) {
-      f.a[k] = sm.A[sme][i][k];
-      bad |= !finite2(f.a[k]);
-      rowsum += sqrtf(f.a[k].x * f.a[k].x + f.a[k].y * f.a[k].y);
-    }
-    const float2 m = sm.M[sme][i];
-    bad |= !finite2(m);
-    bad = gany<UT>(bad);
-    const float norm1 = gmax<UT>(i < a.U ? rowsum : 0.f);
-    int fail;
-    float2 z = factor_solve<UT>(f, i, m, fail);
-    const float d = inv_diag<UT>(f);
+    const bool live = sme < nvalid;
+    LocalSolve<UT> r;
+    local_solve<UT>(r, sm, sme, i, a.U);
+    if constexpr (PREC != PREC_FP32) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
-    if constexpr (PREC != PREC_FP32) {
-      __syncthreads();
-      sm.M[sme][i] = z;
-      __syncthreads();
-      for (int s = 0; s < NSYS; ++s) {
-        const int idx2 = base + s;
-        const int wl2 = idx2 / C, c2 = idx2 - (idx2 / C) * C;
-        const int w2 = w0 + wl2;
-        if (idx2 < ntot && w2 < a.W) {
-          const float2 zc = sm.M[s][lane % UT];
-          float2 n = residual_mf<UT>(a.H + (size_t)w2 * HB, a.y + (size_t)w2 * a.B, a.U,
-                                     a.off[c2], a.off[c2 + 1], zc);
-          n.x -= a.rho * zc.x;
-          n.y -= a.rho * zc.y;
-          __syncthreads();
-          if (lane < UT) sm.F[s][lane] = make_float4(n.x, n.y, 0.f, 0.f);
-          __syncthreads();
-        }
-      }
-      __syncthreads();
-      const float4 nv = sm.F[sme][i];
-      const float2 dz = solve<UT>(f, i, make_float2(nv.x, nv.y));
-      if (live) { z.x += dz.x; z.y += dz.y; }
-    }
-
-    const float kappa = norm1 * gsum<UT>(i < a.U ? d : 0.f);
-    const bool routed = live && !bad && (fail != 0 || !(kappa <= EQ_COND_LIMIT));
+    const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
+    const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
     if (live && i == 0) {
-      if (a.info) a.info[(size_t)w * C + c] = (bad ? -1 : fail) | (routed ? EQ_INFO_FP64 : 0);
+      if (a.info) a.info[(size_t)w * C + c] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) sm.routed[wl] = 1;
     }
-    const float s2c = a.n0 * d;
+    const float s2c = a.n0 * r.d;
     __syncthreads();
-    sm.F[sme][i] = live ? (bad ? make_float4(nanv, nanv, nanv, 1.f) : make_float4(z.x, z.y, s2c, 1.f))
+    sm.F[sme][i] = live ? (r.bad ? make_float4(nanv, nanv, nanv, 1.f) : make_float4(r.z.x, r.z.y, s2c, 1.f))
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
     // ---- fusion: lane (wlf, u) adds the clusters of its subcarrier, in c order
     if (wlf < a.spw && i < a.U) {
-      for (int s = 0; s < NSYS; ++s) {
+      for (int s = 0; s < nvalid; ++s) {
         const int idx3 = base + s;
-        if (idx3 >= ntot || idx3 / C != wlf) continue;
+        if (idx3 / C != wlf) continue;
         const float4 v = sm.F[s][i];
-        if (v.w == 0.f) continue;
         if (user_nu) {
           const int c3 = idx3 - wlf * C;
           const float nu = a.nu[((size_t)(w0 + wlf) * C + c3) * a.U + i];

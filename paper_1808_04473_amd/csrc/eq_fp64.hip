@@ -1,171 +1,200 @@
-// FP64 re-solve of the subcarriers queued by the forward kernels.
+// FP64 re-solve of the systems queued by the forward kernels.
 //
-// The queue holds subcarriers for which some local (FD) or fused (PD) matrix
-// A = G + rho I had a condition estimate above EQ_COND_LIMIT or a failed FP32
-// pivot.  One 64-lane workgroup recomputes such a subcarrier from the
-// complex64 inputs with FP64 arithmetic: Gram and MRC (Section II-C), the
-// Cholesky factor, z = A^{-1} y^MRC, d = diag(A^{-1}) and, for FD, the fusion
-// of eq. (fusionrule) with the weights of Lemma 1.  It is rare and simple:
-// a plain LDS-resident algorithm, no tiling.
-#include "eq_common.h"
+// The queue holds subcarriers (or ragged systems) for which some local (FD)
+// or fused (PD) matrix A = G + rho I had a condition estimate above
+// EQ_COND_LIMIT or a failed FP32 pivot.  One 64-lane workgroup recomputes
+// such a system from the complex64 inputs with FP64 arithmetic: Gram and MRC
+// (Section II-C), the Cholesky factor, z = A^{-1} y^MRC, d = diag(A^{-1}) and,
+// for FD, the fusion of eq. (fusionrule) with the weights of Lemma 1.  It is
+// rare and simple: a plain LDS-resident algorithm, no tiling.
+#include "eq_ragged.h"
 
 namespace dbpeq {
 
-struct Dc { double x, y; };
+struct Dc {
+  double x, y;
+};
 
 __device__ __forceinline__ Dc dmulc(Dc a, Dc b) {  // a * conj(b)
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 __device__ __forceinline__ Dc dmul(Dc a, Dc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-template <bool FD>
-__global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
-  __shared__ Dc L[EQ_MAX_U][EQ_MAX_U + 1];
-  __shared__ Dc X[EQ_MAX_U][EQ_MAX_U + 1];  // X[j][u] = (L^{-1})_ju
-  __shared__ Dc m[EQ_MAX_U];
-  __shared__ Dc t[EQ_MAX_U];
-  __shared__ int fail;
+struct F64Smem {
+  Dc L[EQ_MAX_U][EQ_MAX_U + 1];
+  Dc X[EQ_MAX_U][EQ_MAX_U + 1];  // X[j][u] = (L^{-1})_ju
+  Dc m[EQ_MAX_U];
+  Dc t[EQ_MAX_U];
+  int fail;
+};
+
+// Re-solves one system.  Clusters c = 0..nclus-1 own rows off(c)..off(c+1)-1
+// (PD passes one cluster covering every row); nu_w = [C][U] user weights or
+// nullptr; on_info(c, fail) reports each cluster's FP64 pivot status.
+template <class Off, class Info>
+__device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
+                            int U, int nclus, Off off, double n0, double rho, bool fd,
+                            const float *nu_w, float2 *zw, float *s2w, Info on_info) {
   const int tid = threadIdx.x;
-  const int U = a.U;
-  const int n = *a.fb_count;
-  const double rho = (double)a.n0 / (double)a.es;
-  const size_t HB = (size_t)a.B * U;
-  for (int q = blockIdx.x; q < n; q += gridDim.x) {
-    const int w = a.fb_list[q];
-    const float2 *Hw = a.H + (size_t)w * HB;
-    const float2 *yw = a.y + (size_t)w * a.B;
-    const int nsys = FD ? a.C : 1;
-    // fusion sums of thread u
-    double sw = 0.0, szx = 0.0, szy = 0.0, sv = 0.0;
-    bool any_bad = false;
-    for (int c = 0; c < nsys; ++c) {
-      const int r0 = FD ? a.off[c] : 0;
-      const int r1 = FD ? a.off[c + 1] : a.B;
-      // Gram (lower triangle) and MRC
-      for (int p = tid; p < U * U; p += 64) {
-        const int i = p / U, j = p % U;
-        if (j > i) continue;
-        Dc acc = {0.0, 0.0};
-        for (int b = r0; b < r1; ++b) {
-          const float2 hi = Hw[(size_t)b * U + i], hj = Hw[(size_t)b * U + j];
-          // conj(H_bi) H_bj
-          acc.x += (double)hi.x * hj.x + (double)hi.y * hj.y;
-          acc.y += (double)hi.x * hj.y - (double)hi.y * hj.x;
-        }
-        if (i == j) acc.x += rho;
-        L[i][j] = acc;
+  double sw = 0.0, szx = 0.0, szy = 0.0, sv = 0.0;
+  bool any_bad = false;
+  for (int c = 0; c < nclus; ++c) {
+    const int r0 = off(c), r1 = off(c + 1);
+    // Gram (lower triangle) + rho I and MRC
+    for (int p = tid; p < U * U; p += 64) {
+      const int i = p / U, j = p % U;
+      if (j > i) continue;
+      Dc acc = {0.0, 0.0};
+      for (int b = r0; b < r1; ++b) {
+        const float2 hi = Hw[(size_t)b * U + i], hj = Hw[(size_t)b * U + j];
+        acc.x += (double)hi.x * hj.x + (double)hi.y * hj.y;
+        acc.y += (double)hi.x * hj.y - (double)hi.y * hj.x;
       }
-      if (tid < U) {
-        Dc acc = {0.0, 0.0};
-        for (int b = r0; b < r1; ++b) {
-          const float2 h = Hw[(size_t)b * U + tid], yv = yw[b];
-          acc.x += (double)h.x * yv.x + (double)h.y * yv.y;
-          acc.y += (double)h.x * yv.y - (double)h.y * yv.x;
-        }
-        m[tid] = acc;
-      }
-      if (tid == 0) fail = 0;
-      __syncthreads();
-      // Cholesky, column by column (A = L L^H, lower triangle in place)
-      for (int j = 0; j < U; ++j) {
-        if (tid == 0) {
-          double s = L[j][j].x;
-          for (int k = 0; k < j; ++k) s -= L[j][k].x * L[j][k].x + L[j][k].y * L[j][k].y;
-          if (!(s > 0.0) && fail == 0) fail = j + 1;
-          L[j][j] = {sqrt(s), 0.0};
-        }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < U; i += 64) {
-          Dc s = L[i][j];
-          for (int k = 0; k < j; ++k) {
-            const Dc p = dmulc(L[i][k], L[j][k]);
-            s.x -= p.x;
-            s.y -= p.y;
-          }
-          L[i][j] = {s.x / L[j][j].x, s.y / L[j][j].x};
-        }
-        __syncthreads();
-      }
-      // forward substitution t = L^{-1} m (thread 0) and columns of L^{-1} (thread u)
-      if (tid == 0) {
-        for (int i = 0; i < U; ++i) {
-          Dc s = m[i];
-          for (int k = 0; k < i; ++k) {
-            const Dc p = dmul(L[i][k], t[k]);
-            s.x -= p.x;
-            s.y -= p.y;
-          }
-          t[i] = {s.x / L[i][i].x, s.y / L[i][i].x};
-        }
-      }
-      if (tid < U) {
-        const int u = tid;
-        for (int j = 0; j < U; ++j) {
-          Dc s = {j == u ? 1.0 : 0.0, 0.0};
-          for (int k = u; k < j; ++k) {
-            const Dc p = dmul(L[j][k], X[k][u]);
-            s.x -= p.x;
-            s.y -= p.y;
-          }
-          X[j][u] = j < u ? Dc{0.0, 0.0} : Dc{s.x / L[j][j].x, s.y / L[j][j].x};
-        }
-      }
-      __syncthreads();
-      if (tid < U) {
-        const int u = tid;
-        double d = 0.0;
-        Dc z = {0.0, 0.0};
-        for (int j = u; j < U; ++j) {
-          d += X[j][u].x * X[j][u].x + X[j][u].y * X[j][u].y;
-          // conj(X_ju) t_j
-          z.x += X[j][u].x * t[j].x + X[j][u].y * t[j].y;
-          z.y += X[j][u].x * t[j].y - X[j][u].y * t[j].x;
-        }
-        const double s2 = (double)a.n0 * d;
-        if (FD) {
-          if (a.nu) {
-            const double nu = a.nu[((size_t)w * a.C + c) * U + u];
-            szx += nu * z.x;
-            szy += nu * z.y;
-            sv += nu * nu * s2;
-          } else {
-            const double p = 1.0 / s2;
-            sw += p;
-            szx += p * z.x;
-            szy += p * z.y;
-          }
-        } else {
-          szx = z.x;
-          szy = z.y;
-          sv = s2;
-        }
-        if (fail) any_bad = true;
-      }
-      if (tid == 0 && a.info) {
-        const size_t ii = FD ? (size_t)w * a.C + c : (size_t)w;
-        const int prev = a.info[ii];
-        a.info[ii] = fail | (prev & EQ_INFO_FP64);
-      }
-      __syncthreads();
+      if (i == j) acc.x += rho;
+      sm.L[i][j] = acc;
     }
     if (tid < U) {
-      double zx, zy, so;
-      if (FD && !a.nu) {
-        zx = szx / sw;
-        zy = szy / sw;
-        so = 1.0 / sw;
-      } else {
-        zx = szx;
-        zy = szy;
-        so = sv;
+      Dc acc = {0.0, 0.0};
+      for (int b = r0; b < r1; ++b) {
+        const float2 h = Hw[(size_t)b * U + tid], yv = yw[b];
+        acc.x += (double)h.x * yv.x + (double)h.y * yv.y;
+        acc.y += (double)h.x * yv.y - (double)h.y * yv.x;
       }
-      if (any_bad) {
-        zx = zy = so = __longlong_as_double(0x7ff8000000000000ll);
+      sm.m[tid] = acc;
+    }
+    if (tid == 0) sm.fail = 0;
+    __syncthreads();
+    // Cholesky A = L L^H, column by column, lower triangle in place
+    for (int j = 0; j < U; ++j) {
+      if (tid == 0) {
+        double s = sm.L[j][j].x;
+        for (int k = 0; k < j; ++k) s -= sm.L[j][k].x * sm.L[j][k].x + sm.L[j][k].y * sm.L[j][k].y;
+        if (!(s > 0.0) && sm.fail == 0) sm.fail = j + 1;
+        sm.L[j][j] = {sqrt(s), 0.0};
       }
-      a.z[(size_t)w * U + tid] = make_float2((float)zx, (float)zy);
-      if (a.s2) a.s2[(size_t)w * U + tid] = (float)so;
+      __syncthreads();
+      for (int i = j + 1 + tid; i < U; i += 64) {
+        Dc s = sm.L[i][j];
+        for (int k = 0; k < j; ++k) {
+          const Dc p = dmulc(sm.L[i][k], sm.L[j][k]);
+          s.x -= p.x;
+          s.y -= p.y;
+        }
+        sm.L[i][j] = {s.x / sm.L[j][j].x, s.y / sm.L[j][j].x};
+      }
+      __syncthreads();
+    }
+    // t = L^{-1} m (thread 0) and the columns of L^{-1} (thread u)
+    if (tid == 0) {
+      for (int i = 0; i < U; ++i) {
+        Dc s = sm.m[i];
+        for (int k = 0; k < i; ++k) {
+          const Dc p = dmul(sm.L[i][k], sm.t[k]);
+          s.x -= p.x;
+          s.y -= p.y;
+        }
+        sm.t[i] = {s.x / sm.L[i][i].x, s.y / sm.L[i][i].x};
+      }
+    }
+    if (tid < U) {
+      const int u = tid;
+      for (int j = 0; j < U; ++j) {
+        Dc s = {j == u ? 1.0 : 0.0, 0.0};
+        for (int k = u; k < j; ++k) {
+          const Dc p = dmul(sm.L[j][k], sm.X[k][u]);
+          s.x -= p.x;
+          s.y -= p.y;
+        }
+        sm.X[j][u] = j < u ? Dc{0.0, 0.0} : Dc{s.x / sm.L[j][j].x, s.y / sm.L[j][j].x};
+      }
     }
     __syncthreads();
+    if (tid < U) {
+      const int u = tid;
+      double d = 0.0;
+      Dc z = {0.0, 0.0};
+      for (int j = u; j < U; ++j) {
+        d += sm.X[j][u].x * sm.X[j][u].x + sm.X[j][u].y * sm.X[j][u].y;
+        z.x += sm.X[j][u].x * sm.t[j].x + sm.X[j][u].y * sm.t[j].y;  // conj(X_ju) t_j
+        z.y += sm.X[j][u].x * sm.t[j].y - sm.X[j][u].y * sm.t[j].x;
+      }
+      const double s2 = n0 * d;
+      if (fd) {
+        if (nu_w) {
+          const double nu = nu_w[(size_t)c * U + u];
+          szx += nu * z.x;
+          szy += nu * z.y;
+          sv += nu * nu * s2;
+        } else {
+          const double p = 1.0 / s2;
+          sw += p;
+          szx += p * z.x;
+          szy += p * z.y;
+        }
+      } else {
+        szx = z.x;
+        szy = z.y;
+        sv = s2;
+      }
+      if (sm.fail) any_bad = true;
+    }
+    if (tid == 0) on_info(c, sm.fail);
+    __syncthreads();
+  }
+  if (tid < U) {
+    double zx, zy, so;
+    if (fd && !nu_w) {
+      zx = szx / sw;
+      zy = szy / sw;
+      so = 1.0 / sw;
+    } else {
+      zx = szx;
+      zy = szy;
+      so = sv;
+    }
+    if (any_bad) zx = zy = so = __longlong_as_double(0x7ff8000000000000ll);
+    zw[tid] = make_float2((float)zx, (float)zy);
+    if (s2w) s2w[tid] = (float)so;
+  }
+  __syncthreads();
+}
+
+template <bool FD>
+__global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
+  __shared__ F64Smem sm;
+  const int n = *a.fb_count;
+  const double rho = (double)a.n0 / (double)a.es;
+  const size_t HB = (size_t)a.B * a.U;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int w = a.fb_list[q];
+    auto off = [&](int c) { return FD ? (int)a.off[c] : (c == 0 ? 0 : a.B); };
+    auto info = [&](int c, int fail) {
+      if (!a.info) return;
+      const size_t ii = FD ? (size_t)w * a.C + c : (size_t)w;
+      a.info[ii] = fail | (a.info[ii] & EQ_INFO_FP64);
+    };
+    fp64_system(sm, a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, FD ? a.C : 1, off,
+                (double)a.n0, rho, FD, a.nu ? a.nu + (size_t)w * a.C * a.U : nullptr,
+                a.z + (size_t)w * a.U, a.s2 ? a.s2 + (size_t)w * a.U : nullptr, info);
+  }
+}
+
+template <bool FD>
+__global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) {
+  __shared__ F64Smem sm;
+  const int n = *a.fb_count;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int k = a.fb_list[q];
+    const RSys d = a.sys[k];
+    auto off = [&](int c) { return FD ? a.offs[d.off_first + c] : (c == 0 ? 0 : d.B); };
+    int worst = 0;
+    auto info = [&](int c, int fail) {
+      if (fail && !worst) worst = fail;
+    };
+    fp64_system(sm, a.Hpool + d.h_off, a.ypool + d.y_off, d.U, FD ? d.C : 1, off, (double)d.n0,
+                (double)d.n0 / (double)a.es, FD, nullptr, a.zpool + d.z_off,
+                a.s2pool ? a.s2pool + d.z_off : nullptr, info);
+    if (threadIdx.x == 0 && a.info) a.info[k] = worst | EQ_INFO_FP64;
   }
 }
 
@@ -175,6 +204,15 @@ hipError_t launch_fp64_resolve(const FwdArgs &a, bool fd, hipStream_t s) {
     hipLaunchKernelGGL((eq_fp64_kernel<true>), dim3(grid), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL((eq_fp64_kernel<false>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp64_ragged(const RaggedArgs &a, bool fd, hipStream_t s) {
+  const int grid = a.nsys < 512 ? (a.nsys > 0 ? a.nsys : 1) : 512;
+  if (fd)
+    hipLaunchKernelGGL((eq_fp64_ragged_kernel<true>), dim3(grid), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((eq_fp64_ragged_kernel<false>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,404 @@
+// Ragged-batch plans: host-side descriptor table, cost-sorted work items, the
+// launch-shape autotuner (with a JSON cache) and hipGraph capture of the
+// persistent launch.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "eq_ragged.h"
+
+using namespace dbpeq;
+
+struct eq_plan {
+  int fd = 0, prec = 0;
+  float es = 1.f;
+  int nsys = 0;
+  std::vector<RSys> sys;
+  std::vector<int32_t> offs;
+  // tuned launch shape
+  int grid = 0;       // persistent workgroups (one wave each)
+  int half = 0;       // PD: 1 = work items of half a round of systems
+  bool tuned = false;
+  std::string cache_path, key;
+  // device memory owned by the plan
+  RSys *d_sys = nullptr;
+  int32_t *d_offs = nullptr;
+  RTask *d_tasks = nullptr;
+  int32_t *d_order = nullptr;
+  int32_t *d_scratch = nullptr;  // [0] queue head, [1] FP64 count, [64..] FP64 list
+  int ntasks = 0;
+  int tasks_half = -1;            // `half` the device task table was built for
+  // captured graph and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *gargs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t cap = nullptr;
+};
+
+namespace {
+
+double sys_cost(const RSys &d, bool fd) {
+  const double ut = d.ut;
+  // Gram work (B * UT^2) plus the small solves (UT^3 per system or cluster)
+  return (double)d.B * ut * ut + (fd ? d.C : 1) * ut * ut * ut * 4.0;
+}
+
+// Work items: FD = one system each; PD = up to `per` systems of equal U.
+void build_tasks(const eq_plan &p, int half, std::vector<RTask> &tasks, std::vector<int32_t> &order) {
+  std::vector<int32_t> idx(p.nsys);
+  for (int k = 0; k < p.nsys; ++k) idx[k] = k;
+  const bool fd = p.fd != 0;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (!fd && p.sys[a].U != p.sys[b].U) return p.sys[a].U < p.sys[b].U;
+    return sys_cost(p.sys[a], fd) > sys_cost(p.sys[b], fd);
+  });
+  order = idx;
+  tasks.clear();
+  std::vector<double> cost;
+  int k = 0;
+  while (k < p.nsys) {
+    const RSys &d = p.sys[idx[k]];
+    int per = fd ? 1 : 64 / d.ut;
+    if (!fd && half) per = per > 1 ? per / 2 : 1;
+    int n = 0;
+    double c = 0.0;
+    while (n < per && k + n < p.nsys && p.sys[idx[k + n]].U == d.U) {
+      c += sys_cost(p.sys[idx[k + n]], fd);
+      ++n;
+    }
+    tasks.push_back(RTask{k, n, d.ut, d.U});
+    cost.push_back(c);
+    k += n;
+  }
+  // largest items first
+  std::vector<int> ti(tasks.size());
+  for (size_t t = 0; t < ti.size(); ++t) ti[t] = (int)t;
+  std::stable_sort(ti.begin(), ti.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<RTask> sorted;
+  for (int t : ti) sorted.push_back(tasks[t]);
+  tasks.swap(sorted);
+}
+
+eq_status upload_tasks(eq_plan *p, int half) {
+  if (p->tasks_half == half) return EQ_OK;
+  std::vector<RTask> tasks;
+  std::vector<int32_t> order;
+  build_tasks(*p, half, tasks, order);
+  if (p->d_tasks) hipFree(p->d_tasks);
+  p->d_tasks = nullptr;
+  if (hipMalloc(&p->d_tasks, sizeof(RTask) * tasks.size()) != hipSuccess) return EQ_ENOMEM;
+  if (hipMemcpy(p->d_tasks, tasks.data(), sizeof(RTask) * tasks.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return EQ_EHIP;
+  if (hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return EQ_EHIP;
+  p->ntasks = (int)tasks.size();
+  p->tasks_half = half;
+  return EQ_OK;
+}
+
+std::string plan_key(const eq_plan &p) {
+  // shape signature: FNV-1a over every (B, U, C, cluster sizes), in order
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  for (const RSys &d : p.sys) {
+    mix(d.B);
+    mix(d.U);
+    mix(d.C);
+  }
+  for (int32_t o : p.offs) mix((uint64_t)o);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "gfx950/%s/p%d/n%d/%016llx", p.fd ? "fd" : "pd", p.prec, p.nsys,
+           (unsigned long long)h);
+  return buf;
+}
+
+// The cache is a JSON object with one entry per line:
+//   "key": {"grid": G, "half": H},
+std::map<std::string, std::pair<int, int>> read_cache(const std::string &path) {
+  std::map<std::string, std::pair<int, int>> m;
+  if (path.empty()) return m;
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return m;
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    char key[256];
+    int g = 0, hf = 0;
+    if (sscanf(line, " \"%255[^\"]\": {\"grid\": %d, \"half\": %d}", key, &g, &hf) == 3 && g > 0 &&
+        (hf == 0 || hf == 1))
+      m[key] = {g, hf};
+  }
+  fclose(f);
+  return m;
+}
+
+void write_cache(const std::string &path, const std::map<std::string, std::pair<int, int>> &m) {
+  if (path.empty()) return;
+  const std::string tmp = path + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t n = 0;
+  for (const auto &kv : m) {
+    ++n;
+    fprintf(f, "  \"%s\": {\"grid\": %d, \"half\": %d}%s\n", kv.first.c_str(), kv.second.first,
+            kv.second.second, n < m.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path.c_str());
+}
+
+RaggedArgs make_args(const eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *s2, int32_t *info) {
+  RaggedArgs a;
+  memset(&a, 0, sizeof(a));
+  a.Hpool = reinterpret_cast<const float2 *>(H);
+  a.ypool = reinterpret_cast<const float2 *>(y);
+  a.zpool = reinterpret_cast<float2 *>(z);
+  a.s2pool = s2;
+  a.info = info;
+  a.sys = p->d_sys;
+  a.offs = p->d_offs;
+  a.tasks = p->d_tasks;
+  a.order = p->d_order;
+  a.counter = p->d_scratch;
+  a.fb_count = p->d_scratch + 1;
+  a.fb_list = p->d_scratch + 64;
+  a.nsys = p->nsys;
+  a.ntasks = p->ntasks;
+  a.es = p->es;
+  return a;
+}
+
+hipError_t enqueue(const eq_plan *p, const RaggedArgs &a, int grid, hipStream_t s) {
+  hipError_t e = launch_zero_i32(p->d_scratch, 2, s);
+  if (e != hipSuccess) return e;
+  e = launch_ragged(a, p->fd != 0, p->prec, grid, s);
+  if (e != hipSuccess) return e;
+  return launch_fp64_ragged(a, p->fd != 0, s);
+}
+
+// Times every launch shape on the real pools and keeps the fastest.
+eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *s2, int32_t *info,
+                   hipStream_t s) {
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const int waves[] = {1, 2, 4, 8};
+  const int nh = p->fd ? 1 : 2;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EQ_EHIP;
+  float best = 1e30f;
+  int bg = cus * 2, bh = 0;
+  for (int hf = 0; hf < nh; ++hf) {
+    eq_status st = upload_tasks(p, hf);
+    if (st != EQ_OK) return st;
+    for (int wv : waves) {
+      const int grid = cus * wv;
+      RaggedArgs a = make_args(p, H, y, z, s2, info);
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        hipEventRecord(e0, s);
+        if (enqueue(p, a, grid, s) != hipSuccess) return EQ_EHIP;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) return EQ_EHIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        tmin = ms < tmin ? ms : tmin;
+      }
+      if (tmin < best) {
+        best = tmin;
+        bg = grid;
+        bh = hf;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  p->grid = bg;
+  p->half = bh;
+  p->tuned = true;
+  auto m = read_cache(p->cache_path);
+  m[p->key] = {bg, bh};
+  write_cache(p->cache_path, m);
+  return EQ_OK;
+}
+
+void drop_graph(eq_plan *p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const int32_t *sizes,
+                         int32_t nsizes, int32_t fd, int32_t precision, float es,
+                         const char *tune_cache_path) {
+  if (!out) return EQ_EINVAL;
+  *out = nullptr;
+  if (nsys < 1 || !desc || !sizes || nsizes < 1) return EQ_EINVAL;
+  if (fd != 0 && fd != 1) return EQ_EINVAL;
+  if (precision < EQ_FP32 || precision > EQ_BF16X3_REFINE) return EQ_EINVAL;
+  if (!isfinite(es) || !(es > 0.f)) return EQ_EINVAL;
+  eq_plan *p = new eq_plan();
+  p->fd = fd;
+  p->prec = precision;
+  p->es = es;
+  p->nsys = nsys;
+  p->sys.resize(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    const eq_sys &d = desc[k];
+    const bool ok = d.B >= 1 && d.B <= EQ_MAX_B && d.U >= 1 && d.C >= 1 && d.C <= d.B &&
+                    d.C <= EQ_MAX_C && d.h_off >= 0 && d.y_off >= 0 && d.z_off >= 0 &&
+                    d.clus_first >= 0 && (int64_t)d.clus_first + d.C <= nsizes && isfinite(d.n0) &&
+                    d.n0 > 0.f && isfinite(d.n0 / es) && d.n0 / es > 0.f;
+    if (!ok) {
+      delete p;
+      return d.U > EQ_MAX_U || d.B > EQ_MAX_B ? EQ_ENOTSUP : EQ_EINVAL;
+    }
+    if (d.U > EQ_MAX_U) {
+      delete p;
+      return EQ_ENOTSUP;
+    }
+    RSys &r = p->sys[k];
+    r.h_off = d.h_off;
+    r.y_off = d.y_off;
+    r.z_off = d.z_off;
+    r.B = d.B;
+    r.U = d.U;
+    r.C = d.C;
+    r.n0 = d.n0;
+    r.rho = d.n0 / es;
+    r.ut = ut_for(d.U);
+    r.pad = 0;
+    r.off_first = (int32_t)p->offs.size();
+    int acc = 0;
+    p->offs.push_back(0);
+    for (int c = 0; c < d.C; ++c) {
+      const int sz = sizes[d.clus_first + c];
+      if (sz < 1) {
+        delete p;
+        return EQ_EINVAL;
+      }
+      acc += sz;
+      p->offs.push_back(acc);
+    }
+    if (acc != d.B) {
+      delete p;
+      return EQ_EINVAL;
+    }
+  }
+  p->cache_path = tune_cache_path ? tune_cache_path : (getenv("DBPEQ_TUNE_CACHE") ? getenv("DBPEQ_TUNE_CACHE") : "");
+  p->key = plan_key(*p);
+  auto m = read_cache(p->cache_path);
+  auto it = m.find(p->key);
+  if (it != m.end()) {
+    p->grid = it->second.first;
+    p->half = it->second.second;
+    p->tuned = true;
+  }
+  bool ok = hipMalloc(&p->d_sys, sizeof(RSys) * nsys) == hipSuccess &&
+            hipMalloc(&p->d_offs, sizeof(int32_t) * p->offs.size()) == hipSuccess &&
+            hipMalloc(&p->d_order, sizeof(int32_t) * nsys) == hipSuccess &&
+            hipMalloc(&p->d_scratch, sizeof(int32_t) * (64 + (size_t)nsys)) == hipSuccess;
+  if (!ok) {
+    eq_plan_destroy(p);
+    return EQ_ENOMEM;
+  }
+  if (hipMemcpy(p->d_sys, p->sys.data(), sizeof(RSys) * nsys, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_offs, p->offs.data(), sizeof(int32_t) * p->offs.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    eq_plan_destroy(p);
+    return EQ_EHIP;
+  }
+  eq_status st = upload_tasks(p, p->tuned ? p->half : 0);
+  if (st != EQ_OK) {
+    eq_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return EQ_OK;
+}
+
+eq_status eq_plan_execute(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *s2, int32_t *info,
+                          void *stream) {
+  if (!p || !H || !y || !z) return EQ_EINVAL;
+  if (((uintptr_t)H % 8) || ((uintptr_t)y % 8) || ((uintptr_t)z % 8) || ((uintptr_t)s2 % 4) ||
+      ((uintptr_t)info % 4))
+    return EQ_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!p->tuned) {
+    drop_graph(p);
+    eq_status st = autotune(p, H, y, z, s2, info, s);
+    if (st != EQ_OK) return st;
+  }
+  eq_status st = upload_tasks(p, p->half);
+  if (st != EQ_OK) return st;
+  const void *args[5] = {H, y, z, s2, info};
+  bool same = p->exec != nullptr;
+  for (int k = 0; k < 5 && same; ++k) same = args[k] == p->gargs[k];
+  if (!same) {
+    drop_graph(p);
+    if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) return EQ_EHIP;
+    // the captured launches must not run before the caller's prior work
+    RaggedArgs a = make_args(p, H, y, z, s2, info);
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed) != hipSuccess) return EQ_EHIP;
+    hipError_t e = enqueue(p, a, p->grid, p->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      return EQ_EHIP;
+    }
+    p->graph = g;
+    if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(p);
+      return EQ_EHIP;
+    }
+    for (int k = 0; k < 5; ++k) p->gargs[k] = args[k];
+  }
+  if (hipGraphLaunch(p->exec, s) != hipSuccess) return EQ_EHIP;
+  return EQ_OK;
+}
+
+eq_status eq_plan_describe(const eq_plan *p, int32_t *out_waves, int32_t *out_tasks) {
+  if (!p) return EQ_EINVAL;
+  if (out_waves) {
+    out_waves[0] = p->grid;
+    out_waves[1] = p->half;
+  }
+  if (out_tasks) *out_tasks = p->ntasks;
+  return EQ_OK;
+}
+
+eq_status eq_plan_destroy(eq_plan *p) {
+  if (!p) return EQ_OK;
+  drop_graph(p);
+  if (p->cap) hipStreamDestroy(p->cap);
+  if (p->d_sys) hipFree(p->d_sys);
+  if (p->d_offs) hipFree(p->d_offs);
+  if (p->d_tasks) hipFree(p->d_tasks);
+  if (p->d_order) hipFree(p->d_order);
+  if (p->d_scratch) hipFree(p->d_scratch);
+  delete p;
+  return EQ_OK;
+}
+
+}  // extern "C"

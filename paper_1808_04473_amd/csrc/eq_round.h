@@ -1,0 +1,80 @@
+// Per-wave round state shared by the forward and backward kernels: the LDS
+// staging of a round of NSYS = 64/UT small systems and the per-group
+// factorisation of one system.
+#pragma once
+#include "eq_device.h"
+
+namespace dbpeq {
+
+template <int UT>
+struct Smem {
+  static constexpr int NSYS = 64 / UT;
+  float2 A[NSYS][UT][UT + 1];
+  float2 M[NSYS][UT];
+  float4 F[NSYS][UT];
+  int routed[NSYS];
+};
+
+// Loads row i of system `sme` from LDS and factorises / solves it.
+template <int UT>
+struct LocalSolve {
+  Factor<UT> f;
+  float2 z;
+  float d;
+  float norm1;
+  int fail;
+  bool bad;
+};
+
+template <int UT>
+__device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int sme, int i, int U) {
+  bool bad = false;
+  float rowsum = 0.f;
+#pragma unroll
+  for (int k = 0; k < UT; ++k) {
+    r.f.a[k] = sm.A[sme][i][k];
+    bad |= !finite2(r.f.a[k]);
+    rowsum += sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
+  }
+  const float2 m = sm.M[sme][i];
+  bad |= !finite2(m);
+  r.bad = gany<UT>(bad);
+  r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
+  r.z = factor_solve<UT>(r.f, i, m, r.fail);
+  r.d = inv_diag<UT>(r.f);
+}
+
+// One refinement step for the systems of a round: every group's z goes to
+// LDS, the residual pass streams the systems' rows again and each group
+// solves A dz = H^H (y - H z) - rho z with its existing factor.
+template <int UT, class Rho, class Seg>
+__device__ __forceinline__ void refine_round(LocalSolve<UT> &r, Smem<UT> &sm, int nvalid, int U,
+                                             Rho rhof, Seg seg, bool live) {
+  const int lane = lane_id();
+  const int sme = lane / UT, i = lane % UT;
+  __syncthreads();
+  sm.M[sme][i] = r.z;
+  // park the inverse columns in the (now free) matrix slot while streaming
+#pragma unroll
+  for (int k = 0; k < UT; ++k) sm.A[sme][i][k] = r.f.x[k];
+  __syncthreads();
+  residual_stream<UT>(
+      nvalid, U, seg, [&](int s) { return sm.M[s][lane % UT]; },
+      [&](int s, float2 n) {
+        const float2 zc = sm.M[s][lane % UT];
+        const float rho = rhof(s);
+        if (lane < UT) sm.F[s][lane] = make_float4(n.x - rho * zc.x, n.y - rho * zc.y, 0.f, 0.f);
+      });
+  __syncthreads();
+  asm volatile("" ::: "memory");  // reload the parked columns instead of keeping them live
+#pragma unroll
+  for (int k = 0; k < UT; ++k) r.f.x[k] = sm.A[sme][i][k];
+  const float4 nv = sm.F[sme][i];
+  const float2 dz = solve<UT>(r.f, i, make_float2(nv.x, nv.y));
+  if (live) {
+    r.z.x += dz.x;
+    r.z.y += dz.y;
+  }
+}
+
+}  // namespace dbpeq

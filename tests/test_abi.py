@@ -120,3 +120,27 @@ def test_python_binding_refuses_cpu_tensors(lib):
     y = torch.zeros((2, 4), dtype=torch.complex64)
     with pytest.raises(ValueError):
         api.eq_pd(H, y, 0.1, [0, 4])
+
+
+def test_plan_validation(lib):
+    import ctypes as ct
+    desc = (api.EqSys * 2)()
+    desc[0] = api.EqSys(0, 0, 0, 8, 2, 2, 0, 0.1, 0)
+    desc[1] = api.EqSys(16, 8, 2, 8, 2, 2, 2, 0.1, 0)
+    sizes = np.array([4, 4, 3, 5], np.int32)
+    ps = sizes.ctypes.data_as(ct.POINTER(ct.c_int32))
+    h = ct.c_void_p()
+    # wrong cluster sizes sum (3 + 5 = 8 is fine; make it 9)
+    bad = np.array([4, 4, 4, 5], np.int32)
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, bad.ctypes.data_as(ct.POINTER(ct.c_int32)), 4, 0, 0, 1.0, None) == EINVAL
+    assert lib.eq_plan_create(ct.byref(h), desc, 0, ps, 4, 0, 0, 1.0, None) == EINVAL
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 4, 2, 0, 1.0, None) == EINVAL
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 4, 0, 9, 1.0, None) == EINVAL
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 3, 0, 0, 1.0, None) == EINVAL  # clusters past the table
+    desc[1].n0 = 0.0
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 4, 0, 0, 1.0, None) == EINVAL
+    desc[1].n0 = 0.1
+    desc[1].U = 40
+    assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 4, 0, 0, 1.0, None) == ENOTSUP
+    assert lib.eq_plan_execute(None, A, A, A, A, A, None) == EINVAL
+    assert lib.eq_plan_destroy(None) == 0
