@@ -98,82 +98,59 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
 
   // ---- stream the rows again: grad_H and grad_y
   if (nvalid > 0) {
-    const float2 *Hw, *yw;
-    int r0, r1;
-    seg(0, Hw, yw, r0, r1);
-    int s = 0, rb = r0;
-    Blk cur, nxt;
-    load_blk<UT>(cur, Hw, yw, U, rb, r1);
+    constexpr int RPS = 64 / UT;
+    const int g = lane / UT;
     float2 zc = sm.r.M[0][col], lc = sm.L[0][col];
     float2 qc[UT];
     if (use_q) {
 #pragma unroll
       for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[0][k][col];
     }
-    constexpr int RPS = 64 / UT;
-    const int g = lane / UT;
-    while (true) {
-      const float2 *Hn = Hw, *yn = yw;
-      int sn = s, rbn = rb + RPB, r0n = r0, r1n = r1;
-      const bool last = rbn >= r1;
-      bool more = true;
-      if (last) {
-        sn = s + 1;
-        if (sn < nvalid) {
-          seg(sn, Hn, yn, r0n, r1n);
-          rbn = r0n;
-        } else {
-          more = false;
-        }
-      }
-      if (more) load_blk<UT>(nxt, Hn, yn, U, rbn, r1n);
-      float2 *gHw = a.gH ? a.gH + (Hw - a.H) : nullptr;
-      float2 *gyw = a.gy ? a.gy + (yw - a.y) : nullptr;
+    stream_blocks<UT>(
+        nvalid, U, seg,
+        [&](const Slot &b) {
+          float2 *gHw = a.gH ? a.gH + (b.Hw - a.H) : nullptr;
+          float2 *gyw = a.gy ? a.gy + (b.yw - a.y) : nullptr;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float2 h = cur.h[e];
-        const float hzx = gsum<UT>(h.x * zc.x - h.y * zc.y);
-        const float hzy = gsum<UT>(h.x * zc.y + h.y * zc.x);
-        const float hlx = gsum<UT>(h.x * lc.x - h.y * lc.y);
-        const float hly = gsum<UT>(h.x * lc.y + h.y * lc.x);
-        const float rx = cur.y[e].x - hzx, ry = cur.y[e].y - hzy;
-        // (y - Hz)_row conj(lambda_col) - (H lambda)_row conj(z_col)
-        float gx = rx * lc.x + ry * lc.y - (hlx * zc.x + hly * zc.y);
-        float gy = ry * lc.x - rx * lc.y - (hly * zc.x - hlx * zc.y);
-        if (use_q) {
-          float qx = 0.f, qy = 0.f;
-          sfor<UT>([&](auto K) {
-            constexpr int k = K;
-            const float2 hk = gbcast2<UT, k>(h);
-            qx += hk.x * qc[k].x - hk.y * qc[k].y;
-            qy += hk.x * qc[k].y + hk.y * qc[k].x;
-          });
-          gx -= 2.f * a.n0 * qx;
-          gy -= 2.f * a.n0 * qy;
-        }
-        const int row = rb + e * RPS + g;
-        if (row < r1) {
-          if (gHw && col < U) gHw[(size_t)row * U + col] = make_float2(gx, gy);
-          if (gyw && col == 0) gyw[row] = make_float2(hlx, hly);
-        }
-      }
-      if (!more) break;
-      cur = nxt;
-      s = sn;
-      rb = rbn;
-      Hw = Hn;
-      yw = yn;
-      r0 = r0n;
-      r1 = r1n;
-      if (last) {
-        zc = sm.r.M[s][col];
-        lc = sm.L[s][col];
-        if (use_q) {
+          for (int e = 0; e < 8; ++e) {
+            const float2 h = b.h[e];
+            const float hzx = gsum<UT>(h.x * zc.x - h.y * zc.y);
+            const float hzy = gsum<UT>(h.x * zc.y + h.y * zc.x);
+            const float hlx = gsum<UT>(h.x * lc.x - h.y * lc.y);
+            const float hly = gsum<UT>(h.x * lc.y + h.y * lc.x);
+            const float2 yv = slot_y<UT>(b, e);
+            const float rx = yv.x - hzx, ry = yv.y - hzy;
+            // (y - Hz)_row conj(lambda_col) - (H lambda)_row conj(z_col)
+            float gx = rx * lc.x + ry * lc.y - (hlx * zc.x + hly * zc.y);
+            float gy = ry * lc.x - rx * lc.y - (hly * zc.x - hlx * zc.y);
+            if (use_q) {
+              float qx = 0.f, qy = 0.f;
+              sfor<UT>([&](auto K) {
+                constexpr int k = K;
+                const float2 hk = gbcast2<UT, k>(h);
+                qx += hk.x * qc[k].x - hk.y * qc[k].y;
+                qy += hk.x * qc[k].y + hk.y * qc[k].x;
+              });
+              gx -= 2.f * a.n0 * qx;
+              gy -= 2.f * a.n0 * qy;
+            }
+            const int row = b.rb + e * RPS + g;
+            if (row < b.r1) {
+              if (gHw && col < U) gHw[(size_t)row * U + col] = make_float2(gx, gy);
+              if (gyw && col == 0) gyw[row] = make_float2(hlx, hly);
+            }
+          }
+        },
+        [&](int s) {
+          if (s + 1 < nvalid) {
+            zc = sm.r.M[s + 1][col];
+            lc = sm.L[s + 1][col];
+            if (use_q) {
 #pragma unroll
-          for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[s][k][col];
-        }
-      }
-    }
+              for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[s + 1][k][col];
+            }
+          }
+        });
   }
   __syncthreads();
   return (sme < nvalid && i < U) ? gn0 : 0.f;

@@ -168,18 +168,26 @@ __device__ __forceinline__ void acc_zero(Acc<UT> &a) {
   for (int r = 0; r < NR; ++r) { a.rr[r] = 0.f; a.ri[r] = 0.f; a.ii[r] = 0.f; }
 }
 
-// ---------------------------------------------------------------- Gram + matched filter
+// ---------------------------------------------------------------- row-block streaming
 // One block = 8 load steps = 8 * (64/UT) rows of one system, in the
-// streaming layout (lane: column col, rows rb + e*RPS + g for e = 0..7).
-struct Blk {
+// streaming layout: lane l holds H[rb + e*RPS + g][col] (col = l % UT,
+// g = l / UT, e = 0..7).  y is loaded once per row (lane j < RPB holds
+// y[rb + j]) and handed to the lanes of a row by a lane shuffle: a per-lane
+// copy would cost eight vector-memory instructions for 256 bytes.
+struct Slot {
   float2 h[8];
-  float2 y[8];
+  float2 yl;
+  const float2 *Hw;
+  const float2 *yw;
+  int s, rb, r1;
+  bool last;
 };
 
 template <int UT>
-__device__ __forceinline__ void load_blk(Blk &b, const float2 *__restrict__ Hw,
-                                         const float2 *__restrict__ yw, int U, int rb, int r1) {
+__device__ __forceinline__ void load_slot(Slot &b, const float2 *__restrict__ Hw,
+                                          const float2 *__restrict__ yw, int U, int rb, int r1) {
   constexpr int RPS = 64 / UT;
+  constexpr int RPB = 8 * RPS;
   const int lane = lane_id();
   const int col = lane % UT;
   const int g = lane / UT;
@@ -187,16 +195,73 @@ __device__ __forceinline__ void load_blk(Blk &b, const float2 *__restrict__ Hw,
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int row = rb + e * RPS + g;
-    const bool rv = row < r1;
-    b.h[e] = (rv && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
-    b.y[e] = rv ? yw[row] : make_float2(0.f, 0.f);
+    b.h[e] = (row < r1 && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
+  }
+  const int yrow = rb + lane;
+  b.yl = (lane < RPB && yrow < r1) ? yw[yrow] : make_float2(0.f, 0.f);
+  b.Hw = Hw;
+  b.yw = yw;
+  b.rb = rb;
+  b.r1 = r1;
+}
+
+// y[rb + e*RPS + g] of this lane's row in load step e.
+template <int UT>
+__device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
+  constexpr int RPS = 64 / UT;
+  const int src = e * RPS + lane_id() / UT;
+  return make_float2(__shfl(b.yl.x, src), __shfl(b.yl.y, src));
+}
+
+// Streams the row blocks of systems 0..ns-1 (seg(s, Hw, yw, r0, r1)
+// describes system s) with the loads of the next two blocks in flight while
+// body(slot) consumes the current one; done(s) follows the last block of s.
+template <int UT, class Seg, class Body, class Done>
+__device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body, Done done) {
+  constexpr int RPB = 8 * (64 / UT);
+  if (ns <= 0) return;
+  // load cursor
+  int cs = 0, crb, cr0, cr1;
+  const float2 *cH, *cy;
+  seg(0, cH, cy, cr0, cr1);
+  crb = cr0;
+  bool more = true;
+  auto issue = [&](Slot &sl) {
+    load_slot<UT>(sl, cH, cy, U, crb, cr1);
+    sl.s = cs;
+    sl.last = crb + RPB >= cr1;
+    crb += RPB;
+    if (crb >= cr1) {
+      ++cs;
+      if (cs < ns) {
+        seg(cs, cH, cy, cr0, cr1);
+        crb = cr0;
+      } else {
+        more = false;
+      }
+    }
+  };
+  Slot s0, s1, s2;
+  issue(s0);
+  bool h1 = more;
+  if (h1) issue(s1);
+  while (true) {
+    bool h2 = more;
+    if (h2) issue(s2);
+    body(s0);
+    if (s0.last) done(s0.s);
+    if (!h1) break;
+    s0 = s1;
+    s1 = s2;
+    h1 = h2;
   }
 }
 
+// ---------------------------------------------------------------- Gram + matched filter
 // acc += real split of the block's H^H H (rr = Hr^T Hr, ri = Hr^T Hi,
 // ii = Hi^T Hi); (mfx, mfy) += partial of sum conj(H[row][col]) y[row].
 template <int UT, int PREC>
-__device__ __forceinline__ void gram_blk(const Blk &b, Acc<UT> &acc, float &mfx, float &mfy) {
+__device__ __forceinline__ void gram_blk(const Slot &b, Acc<UT> &acc, float &mfx, float &mfy) {
   if constexpr (PREC == PREC_FP32) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -235,118 +300,59 @@ __device__ __forceinline__ void gram_blk(const Blk &b, Acc<UT> &acc, float &mfx,
   }
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
+    const float2 yv = slot_y<UT>(b, e);
     // conj(h) * y
-    mfx += b.h[e].x * b.y[e].x + b.h[e].y * b.y[e].y;
-    mfy += b.h[e].x * b.y[e].y - b.h[e].y * b.y[e].x;
+    mfx += b.h[e].x * yv.x + b.h[e].y * yv.y;
+    mfy += b.h[e].x * yv.y - b.h[e].y * yv.x;
   }
 }
 
-// Streams the row blocks of `ns` systems back to back with the next block's
-// loads in flight while the current block is multiplied (the prefetch runs
-// across system boundaries).  seg(s, Hw, yw, r0, r1) describes system s;
-// after its last block, done(s, acc, mf) receives its Gram accumulators and
-// matched filter (mf reduced over the lanes of a column).
+// Gram + matched filter of systems 0..ns-1; done(s, acc, mf) receives each
+// system's accumulators and its matched filter (reduced over a column).
 template <int UT, int PREC, class Seg, class Done>
 __device__ __forceinline__ void gram_stream(int ns, int U, Seg seg, Done done) {
-  constexpr int RPB = 8 * (64 / UT);
-  if (ns <= 0) return;
-  const float2 *Hw, *yw;
-  int r0, r1;
-  seg(0, Hw, yw, r0, r1);
-  int s = 0, rb = r0;
-  Blk cur, nxt;
-  load_blk<UT>(cur, Hw, yw, U, rb, r1);
   Acc<UT> acc;
   acc_zero<UT>(acc);
   float mfx = 0.f, mfy = 0.f;
-  while (true) {
-    const float2 *Hn = Hw, *yn = yw;
-    int sn = s, rbn = rb + RPB, r0n = r0, r1n = r1;
-    const bool last = rbn >= r1;
-    bool more = true;
-    if (last) {
-      sn = s + 1;
-      if (sn < ns) {
-        seg(sn, Hn, yn, r0n, r1n);
-        rbn = r0n;
-      } else {
-        more = false;
-      }
-    }
-    if (more) load_blk<UT>(nxt, Hn, yn, U, rbn, r1n);
-    gram_blk<UT, PREC>(cur, acc, mfx, mfy);
-    if (last) {
-      done(s, acc, make_float2(colsum<UT>(mfx), colsum<UT>(mfy)));
-      acc_zero<UT>(acc);
-      mfx = 0.f;
-      mfy = 0.f;
-    }
-    if (!more) break;
-    cur = nxt;
-    s = sn;
-    rb = rbn;
-    Hw = Hn;
-    yw = yn;
-    r0 = r0n;
-    r1 = r1n;
-  }
+  stream_blocks<UT>(
+      ns, U, seg, [&](const Slot &b) { gram_blk<UT, PREC>(b, acc, mfx, mfy); },
+      [&](int s) {
+        done(s, acc, make_float2(colsum<UT>(mfx), colsum<UT>(mfy)));
+        acc_zero<UT>(acc);
+        mfx = 0.f;
+        mfy = 0.f;
+      });
 }
 
-// Residual pass of the refinement step, streamed like gram_stream: for
-// system s (zc(s) gives z[col] of that system in every lane) accumulates
-// n = H^H (y - H z) and calls done(s, n) with n[col] valid in every lane.
+// Residual pass of the refinement step: for system s (zcf(s) gives z[col]
+// of that system) accumulates n = H^H (y - H z) and calls done(s, n) with
+// n[col] valid in every lane.
 template <int UT, class Seg, class Zc, class Done>
 __device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, Done done) {
-  constexpr int RPB = 8 * (64 / UT);
-  if (ns <= 0) return;
-  const float2 *Hw, *yw;
-  int r0, r1;
-  seg(0, Hw, yw, r0, r1);
-  int s = 0, rb = r0;
-  Blk cur, nxt;
-  load_blk<UT>(cur, Hw, yw, U, rb, r1);
-  float2 zc = zcf(0);
   float nx = 0.f, ny = 0.f;
-  while (true) {
-    const float2 *Hn = Hw, *yn = yw;
-    int sn = s, rbn = rb + RPB, r0n = r0, r1n = r1;
-    const bool last = rbn >= r1;
-    bool more = true;
-    if (last) {
-      sn = s + 1;
-      if (sn < ns) {
-        seg(sn, Hn, yn, r0n, r1n);
-        rbn = r0n;
-      } else {
-        more = false;
-      }
-    }
-    if (more) load_blk<UT>(nxt, Hn, yn, U, rbn, r1n);
+  float2 zc = zcf(0);
+  stream_blocks<UT>(
+      ns, U, seg,
+      [&](const Slot &b) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      // (H z)_row = sum over the UT lanes of this row of h * z
-      const float px = gsum<UT>(cur.h[e].x * zc.x - cur.h[e].y * zc.y);
-      const float py = gsum<UT>(cur.h[e].x * zc.y + cur.h[e].y * zc.x);
-      const float rx = cur.y[e].x - px;
-      const float ry = cur.y[e].y - py;
-      nx += cur.h[e].x * rx + cur.h[e].y * ry;
-      ny += cur.h[e].x * ry - cur.h[e].y * rx;
-    }
-    if (last) {
-      done(s, make_float2(colsum<UT>(nx), colsum<UT>(ny)));
-      nx = 0.f;
-      ny = 0.f;
-    }
-    if (!more) break;
-    cur = nxt;
-    s = sn;
-    rb = rbn;
-    Hw = Hn;
-    yw = yn;
-    r0 = r0n;
-    r1 = r1n;
-    if (last) zc = zcf(s);
-  }
+        for (int e = 0; e < 8; ++e) {
+          const float2 h = b.h[e];
+          // (H z)_row = sum over the UT lanes of this row of h * z
+          const float px = gsum<UT>(h.x * zc.x - h.y * zc.y);
+          const float py = gsum<UT>(h.x * zc.y + h.y * zc.x);
+          const float2 yv = slot_y<UT>(b, e);
+          const float rx = yv.x - px;
+          const float ry = yv.y - py;
+          nx += h.x * rx + h.y * ry;
+          ny += h.x * ry - h.y * rx;
+        }
+      },
+      [&](int s) {
+        done(s, make_float2(colsum<UT>(nx), colsum<UT>(ny)));
+        nx = 0.f;
+        ny = 0.f;
+        if (s + 1 < ns) zc = zcf(s + 1);
+      });
 }
 
 // Writes G + rho I of one system from the MFMA accumulators into LDS
