@@ -113,7 +113,7 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
           float2 *gyw = a.gy ? a.gy + (b.yw - a.y) : nullptr;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const float2 h = b.h[e];
+            const float2 h = slot_h<UT>(b, e, U);
             const float hzx = gsum<UT>(h.x * zc.x - h.y * zc.y);
             const float hzy = gsum<UT>(h.x * zc.y + h.y * zc.x);
             const float hlx = gsum<UT>(h.x * lc.x - h.y * lc.y);

@@ -174,6 +174,10 @@ __device__ __forceinline__ void acc_zero(Acc<UT> &a) {
 // g = l / UT, e = 0..7).  y is loaded once per row (lane j < RPB holds
 // y[rb + j]) and handed to the lanes of a row by a lane shuffle: a per-lane
 // copy would cost eight vector-memory instructions for 256 bytes.
+struct Blk8 {
+  float2 h[8];
+};
+
 struct Slot {
   float2 h[8];
   float2 yl;
@@ -183,29 +187,66 @@ struct Slot {
   bool last;
 };
 
+// Loads go through buffer resources that cover exactly the system's rows
+// [r0, r1): the hardware returns zero for any offset outside the range, so
+// rows past r1 and padded columns (col >= U, given an offset that is always
+// out of range) need neither clamping nor masking, and the address of each
+// load is one integer add.  No load sits behind a divergent branch, so the
+// compiler can wait for one block while the next blocks are in flight.
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit buffer, gfx9 format bits
+constexpr unsigned kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return make_float2(v.x, v.y);
+}
+
+// Per-lane byte offsets of the streaming layout (constant over a stream).
 template <int UT>
-__device__ __forceinline__ void load_slot(Slot &b, const float2 *__restrict__ Hw,
-                                          const float2 *__restrict__ yw, int U, int rb, int r1) {
-  constexpr int RPS = 64 / UT;
-  constexpr int RPB = 8 * RPS;
+struct LaneOff {
+  unsigned h;  // (g * U + col) * 8, or out of range for padded columns
+  unsigned y;  // lane * 8 for the lanes that load y, else out of range
+};
+
+template <int UT>
+__device__ __forceinline__ LaneOff<UT> lane_offsets(int U) {
+  constexpr int RPB = 8 * (64 / UT);
   const int lane = lane_id();
-  const int col = lane % UT;
-  const int g = lane / UT;
-  const bool colok = col < U;
+  const int col = lane % UT, g = lane / UT;
+  LaneOff<UT> o;
+  o.h = col < U ? (unsigned)((g * U + col) * 8) : kOutOfRange;
+  o.y = lane < RPB ? (unsigned)(lane * 8) : kOutOfRange;
+  return o;
+}
+
+template <int UT>
+__device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const float2 *__restrict__ Hw,
+                                          const float2 *__restrict__ yw, int U, int rb, int r0,
+                                          int r1) {
+  constexpr int RPS = 64 / UT;
+  const __amdgpu_buffer_rsrc_t rh =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(Hw + (size_t)r0 * U), (short)0, (r1 - r0) * U * 8, kBufFlags);
+  const __amdgpu_buffer_rsrc_t ry =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(yw + r0), (short)0, (r1 - r0) * 8, kBufFlags);
+  const unsigned rowb = (unsigned)((rb - r0) * U * 8);
+  const unsigned step = (unsigned)(RPS * U * 8);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int row = rb + e * RPS + g;
-    b.h[e] = (row < r1 && colok) ? Hw[(size_t)row * U + col] : make_float2(0.f, 0.f);
-  }
-  const int yrow = rb + lane;
-  b.yl = (lane < RPB && yrow < r1) ? yw[yrow] : make_float2(0.f, 0.f);
+  for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2(rh, lo.h + rowb + e * step);
+  b.yl = buf_ld2(ry, lo.y + (unsigned)((rb - r0) * 8));
   b.Hw = Hw;
   b.yw = yw;
   b.rb = rb;
   b.r1 = r1;
 }
 
-// y[rb + e*RPS + g] of this lane's row in load step e.
+// H[rb + e*RPS + g][col] of this lane (zero outside the system).
+template <int UT>
+__device__ __forceinline__ float2 slot_h(const Slot &b, int e, int) {
+  return b.h[e];
+}
+
+// y[rb + e*RPS + g] of this lane's row in load step e (zero past the end).
 template <int UT>
 __device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
   constexpr int RPS = 64 / UT;
@@ -226,34 +267,50 @@ __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body,
   seg(0, cH, cy, cr0, cr1);
   crb = cr0;
   bool more = true;
-  auto issue = [&](Slot &sl) {
-    load_slot<UT>(sl, cH, cy, U, crb, cr1);
+  const LaneOff<UT> lo = lane_offsets<UT>(U);
+  // Every issue executes the same loads: an exhausted stream re-loads its
+  // last block (a cache hit) so that the number of loads in flight is the
+  // same on every path and the compiler can wait for one block at a time.
+  auto issue = [&](Slot &sl) -> bool {
+    const bool valid = more;
+    load_slot<UT>(sl, lo, cH, cy, U, crb, cr0, cr1);
     sl.s = cs;
     sl.last = crb + RPB >= cr1;
-    crb += RPB;
-    if (crb >= cr1) {
-      ++cs;
-      if (cs < ns) {
+    if (valid) {
+      if (crb + RPB < cr1) {
+        crb += RPB;
+      } else if (cs + 1 < ns) {
+        ++cs;
         seg(cs, cH, cy, cr0, cr1);
         crb = cr0;
       } else {
         more = false;
       }
     }
+    return valid;
   };
-  Slot s0, s1, s2;
-  issue(s0);
-  bool h1 = more;
-  if (h1) issue(s1);
+  Slot sa, sb, sc;
+  // sched_barrier keeps each block's loads where they are issued: the
+  // scheduler must not sink them into (or hoist the consumer above) the
+  // previous block's arithmetic.
+  issue(sa);
+  bool vb = issue(sb);
   while (true) {
-    bool h2 = more;
-    if (h2) issue(s2);
-    body(s0);
-    if (s0.last) done(s0.s);
-    if (!h1) break;
-    s0 = s1;
-    s1 = s2;
-    h1 = h2;
+    const bool vc = issue(sc);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sa);
+    if (sa.last) done(sa.s);
+    if (!vb) break;
+    const bool va = issue(sa);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sb);
+    if (sb.last) done(sb.s);
+    if (!vc) break;
+    vb = issue(sb);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sc);
+    if (sc.last) done(sc.s);
+    if (!va) break;
   }
 }
 
@@ -261,7 +318,10 @@ __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body,
 // acc += real split of the block's H^H H (rr = Hr^T Hr, ri = Hr^T Hi,
 // ii = Hi^T Hi); (mfx, mfy) += partial of sum conj(H[row][col]) y[row].
 template <int UT, int PREC>
-__device__ __forceinline__ void gram_blk(const Slot &b, Acc<UT> &acc, float &mfx, float &mfy) {
+__device__ __forceinline__ void gram_blk(const Slot &sl, int U, Acc<UT> &acc, float &mfx, float &mfy) {
+  Blk8 b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) b.h[e] = slot_h<UT>(sl, e, U);
   if constexpr (PREC == PREC_FP32) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -300,10 +360,12 @@ __device__ __forceinline__ void gram_blk(const Slot &b, Acc<UT> &acc, float &mfx
   }
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const float2 yv = slot_y<UT>(b, e);
-    // conj(h) * y
-    mfx += b.h[e].x * yv.x + b.h[e].y * yv.y;
-    mfy += b.h[e].x * yv.y - b.h[e].y * yv.x;
+    const float2 yv = slot_y<UT>(sl, e);
+    // conj(h) * y, accumulated as a chain of FMAs
+    mfx = fmaf(b.h[e].x, yv.x, mfx);
+    mfx = fmaf(b.h[e].y, yv.y, mfx);
+    mfy = fmaf(b.h[e].x, yv.y, mfy);
+    mfy = fmaf(-b.h[e].y, yv.x, mfy);
   }
 }
 
@@ -315,7 +377,7 @@ __device__ __forceinline__ void gram_stream(int ns, int U, Seg seg, Done done) {
   acc_zero<UT>(acc);
   float mfx = 0.f, mfy = 0.f;
   stream_blocks<UT>(
-      ns, U, seg, [&](const Slot &b) { gram_blk<UT, PREC>(b, acc, mfx, mfy); },
+      ns, U, seg, [&](const Slot &b) { gram_blk<UT, PREC>(b, U, acc, mfx, mfy); },
       [&](int s) {
         done(s, acc, make_float2(colsum<UT>(mfx), colsum<UT>(mfy)));
         acc_zero<UT>(acc);
@@ -336,15 +398,17 @@ __device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, 
       [&](const Slot &b) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float2 h = b.h[e];
+          const float2 h = slot_h<UT>(b, e, U);
           // (H z)_row = sum over the UT lanes of this row of h * z
           const float px = gsum<UT>(h.x * zc.x - h.y * zc.y);
           const float py = gsum<UT>(h.x * zc.y + h.y * zc.x);
           const float2 yv = slot_y<UT>(b, e);
           const float rx = yv.x - px;
           const float ry = yv.y - py;
-          nx += h.x * rx + h.y * ry;
-          ny += h.x * ry - h.y * rx;
+          nx = fmaf(h.x, rx, nx);
+          nx = fmaf(h.y, ry, nx);
+          ny = fmaf(h.x, ry, ny);
+          ny = fmaf(-h.y, rx, ny);
         }
       },
       [&](int s) {
