@@ -70,7 +70,11 @@ typedef enum {
   EQ_BF16_REFINE = 1,
   /* As EQ_BF16_REFINE with each operand split into a BF16 high and low part
      (three BF16 products hi*hi + hi*lo + lo*hi per Gram term). */
-  EQ_BF16X3_REFINE = 2
+  EQ_BF16X3_REFINE = 2,
+  /* Split-BF16 Gram on BF16 MFMA with FP32 accumulation, FP32 matched filter
+     and solves, no refinement pass: the Gram is accurate to a few 1e-6
+     relative, which meets the FP32 error bound without a second read of H. */
+  EQ_BF16X3 = 3
 } eq_precision;
 
 /* Shared description of a batch of W systems. */

@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdbpeq.so")
 
-PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+PRECISIONS = {"fp32": 0, "bf16_refine": 1, "bf16x3_refine": 2, "bf16x3": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported problem size",
           -3: "HIP runtime error", -4: "workspace missing or too small",
           -5: "device allocation failed"}

@@ -25,7 +25,7 @@ eq_status check_problem(const eq_problem *p) {
     if (p->cluster_off[c + 1] <= p->cluster_off[c]) return EQ_EINVAL;
   if (!isfinite(p->n0) || !(p->n0 > 0.f)) return EQ_EINVAL;
   if (!isfinite(p->es) || !(p->es > 0.f)) return EQ_EINVAL;
-  if (p->precision < EQ_FP32 || p->precision > EQ_BF16X3_REFINE) return EQ_EINVAL;
+  if (p->precision < EQ_FP32 || p->precision > EQ_BF16X3) return EQ_EINVAL;
   const float rho = p->n0 / p->es;
   if (!isfinite(rho) || !(rho > 0.f)) return EQ_EINVAL;
   return EQ_OK;

@@ -7,7 +7,10 @@
 
 namespace dbpeq {
 
-enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_BF16X3_NR = 3 };
+
+// Forms that run the refinement step with the FP32 residual y - H z.
+constexpr bool refines(int prec) { return prec == PREC_BF16 || prec == PREC_BF16X3; }
 
 // Forward launch arguments (passed by value; the cluster table lives in the
 // kernel-argument segment, so no device-side copy of the host partition is

@@ -183,8 +183,16 @@ struct Slot {
   float2 yl;
   const float2 *Hw;
   const float2 *yw;
-  int s, rb, r1;
+  int s, rb, r1;  // s: system index within its task
+  int tk;         // task the system belongs to
   bool last;
+};
+
+// One system of a stream: rows [r0, r1) of Hw / yw, identified by (tk, s).
+struct SysRef {
+  const float2 *Hw;
+  const float2 *yw;
+  int r0, r1, tk, s;
 };
 
 // Loads go through buffer resources that cover exactly the system's rows
@@ -254,18 +262,17 @@ __device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
   return make_float2(__shfl(b.yl.x, src), __shfl(b.yl.y, src));
 }
 
-// Streams the row blocks of systems 0..ns-1 (seg(s, Hw, yw, r0, r1)
-// describes system s) with the loads of the next two blocks in flight while
-// body(slot) consumes the current one; done(s) follows the last block of s.
-template <int UT, class Seg, class Body, class Done>
-__device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body, Done done) {
+// Streams the row blocks of a sequence of systems produced by gen (a
+// functor bool(SysRef &) returning false at the end of the sequence) with
+// the loads of the next two blocks in flight while body(slot) consumes the
+// current one; done(slot) follows the last block of each system, while the
+// next blocks' loads are still in flight.
+template <int UT, class Gen, class Body, class Done>
+__device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done) {
   constexpr int RPB = 8 * (64 / UT);
-  if (ns <= 0) return;
-  // load cursor
-  int cs = 0, crb, cr0, cr1;
-  const float2 *cH, *cy;
-  seg(0, cH, cy, cr0, cr1);
-  crb = cr0;
+  SysRef cur;
+  if (!gen(cur)) return;
+  int crb = cur.r0;
   bool more = true;
   const LaneOff<UT> lo = lane_offsets<UT>(U);
   // Every issue executes the same loads: an exhausted stream re-loads its
@@ -273,45 +280,112 @@ __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body,
   // same on every path and the compiler can wait for one block at a time.
   auto issue = [&](Slot &sl) -> bool {
     const bool valid = more;
-    load_slot<UT>(sl, lo, cH, cy, U, crb, cr0, cr1);
-    sl.s = cs;
-    sl.last = crb + RPB >= cr1;
+    load_slot<UT>(sl, lo, cur.Hw, cur.yw, U, crb, cur.r0, cur.r1);
+    sl.s = cur.s;
+    sl.tk = cur.tk;
+    sl.last = crb + RPB >= cur.r1;
     if (valid) {
-      if (crb + RPB < cr1) {
+      if (crb + RPB < cur.r1) {
         crb += RPB;
-      } else if (cs + 1 < ns) {
-        ++cs;
-        seg(cs, cH, cy, cr0, cr1);
-        crb = cr0;
       } else {
-        more = false;
+        SysRef nx;
+        if (gen(nx)) {
+          cur = nx;
+          crb = cur.r0;
+        } else {
+          more = false;
+        }
       }
     }
     return valid;
   };
-  Slot sa, sb, sc;
+#ifndef EQ_STREAM_DEPTH
+#define EQ_STREAM_DEPTH 3
+#endif
   // sched_barrier keeps each block's loads where they are issued: the
   // scheduler must not sink them into (or hoist the consumer above) the
   // previous block's arithmetic.
+#if EQ_STREAM_DEPTH == 4
+  // four-slot ring: three blocks in flight while one is consumed
+  Slot sa, sb, sc, sd;
+  issue(sa);
+  bool vb = issue(sb);
+  bool vc = issue(sc);
+  while (true) {
+    const bool vd = issue(sd);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sa);
+    if (sa.last) done(sa);
+    if (!vb) break;
+    const bool va = issue(sa);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sb);
+    if (sb.last) done(sb);
+    if (!vc) break;
+    vb = issue(sb);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sc);
+    if (sc.last) done(sc);
+    if (!vd) break;
+    vc = issue(sc);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sd);
+    if (sd.last) done(sd);
+    if (!va) break;
+  }
+#elif EQ_STREAM_DEPTH == 3
+  Slot sa, sb, sc;
   issue(sa);
   bool vb = issue(sb);
   while (true) {
     const bool vc = issue(sc);
     __builtin_amdgcn_sched_barrier(0);
     body(sa);
-    if (sa.last) done(sa.s);
+    if (sa.last) done(sa);
     if (!vb) break;
     const bool va = issue(sa);
     __builtin_amdgcn_sched_barrier(0);
     body(sb);
-    if (sb.last) done(sb.s);
+    if (sb.last) done(sb);
     if (!vc) break;
     vb = issue(sb);
     __builtin_amdgcn_sched_barrier(0);
     body(sc);
-    if (sc.last) done(sc.s);
+    if (sc.last) done(sc);
     if (!va) break;
   }
+#else
+  // two-slot ring: one block in flight while the other is consumed
+  Slot sa, sb;
+  issue(sa);
+  while (true) {
+    const bool vb = issue(sb);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sa);
+    if (sa.last) done(sa);
+    if (!vb) break;
+    const bool va = issue(sa);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sb);
+    if (sb.last) done(sb);
+    if (!va) break;
+  }
+#endif
+}
+
+// Fixed list of systems 0..ns-1 described by seg(s, Hw, yw, r0, r1);
+// done(s) follows the last block of system s.
+template <int UT, class Seg, class Body, class Done>
+__device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body, Done done) {
+  int next = 0;
+  auto gen = [&](SysRef &r) -> bool {
+    if (next >= ns) return false;
+    seg(next, r.Hw, r.yw, r.r0, r.r1);
+    r.tk = 0;
+    r.s = next++;
+    return true;
+  };
+  stream_gen<UT>(U, gen, body, [&](const Slot &sl) { done(sl.s); });
 }
 
 // ---------------------------------------------------------------- Gram + matched filter
@@ -483,8 +557,9 @@ __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
     constexpr int j = J;
     const float ajj = gbcast<UT, j>(f.a[j].x);
     if (!(ajj > 0.f) && fail == 0) fail = j + 1;
-    const float ljj = sqrtf(ajj);
-    const float inv = 1.0f / ljj;
+    // hardware reciprocal square root (about 1 ulp): 1/L_jj and L_jj = a_jj / sqrt(a_jj)
+    const float inv = __builtin_amdgcn_rsqf(ajj);
+    const float ljj = ajj * inv;
     if (i == j) f.dinv = inv;
     float2 lij = make_float2(f.a[j].x * inv, f.a[j].y * inv);
     if (i == j) lij = make_float2(ljj, 0.f);

@@ -30,15 +30,30 @@ __device__ __forceinline__ void enqueue_fp64(const FwdArgs &a, int w) {
 }
 
 template <int UT, int PREC>
+constexpr int pd_per() {
+  return refines(PREC) && UT == 16 ? 2 : 64 / UT;
+}
+
+// Occupancy target: 4 waves per SIMD (128 VGPRs) for the streaming PD forms,
+// 3 (168 VGPRs, no spills) for FD and for the refining forms.
+template <int UT, int PREC, bool FD>
+constexpr int waves_target() {
+  return (FD || refines(PREC)) ? 3 : EQ_WAVES_PER_EU;
+}
+
+template <int UT, int PREC>
 __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm) {
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
   const int sme = lane / UT;
   const int i = lane % UT;
   const size_t HB = (size_t)a.B * a.U;
-  const int nvalid = min(NSYS, a.W - task * NSYS);
+  // refining forms take half a round of subcarriers per task: the residual
+  // pass then re-reads H soon enough to find it in the Infinity Cache
+  constexpr int PER = pd_per<UT, PREC>();
+  const int nvalid = min(PER, a.W - task * PER);
   auto seg = [&](int s, const float2 *&Hw, const float2 *&yw, int &r0, int &r1) {
-    const size_t w = (size_t)task * NSYS + s;
+    const size_t w = (size_t)task * PER + s;
     Hw = a.H + w * HB;
     yw = a.y + w * a.B;
     r0 = 0;
@@ -58,11 +73,11 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm
   __syncthreads();
 
   // ---- factor and solve: group sme, row/column i
-  const int w = task * NSYS + sme;
+  const int w = task * PER + sme;
   const bool live = sme < nvalid;
   LocalSolve<UT> r;
   local_solve<UT>(r, sm, sme, i, a.U);
-  if constexpr (PREC != PREC_FP32) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
+  if constexpr (refines(PREC)) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
   const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
   const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
@@ -127,7 +142,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
     const bool live = sme < nvalid;
     LocalSolve<UT> r;
     local_solve<UT>(r, sm, sme, i, a.U);
-    if constexpr (PREC != PREC_FP32) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
+    if constexpr (refines(PREC)) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
     const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
     const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
@@ -185,7 +200,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
 }
 
 template <int UT, int PREC, bool FD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(EQ_WAVES_PER_EU, 8))) void eq_forward_kernel(const FwdArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_target<UT, PREC, FD>(), 8))) void eq_forward_kernel(const FwdArgs a) {
   __shared__ Smem<UT> sm;
   if constexpr (FD)
     fd_task<UT, PREC>(a, blockIdx.x, sm);
@@ -203,17 +218,22 @@ hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int UT, int PREC, bool FD>
+static hipError_t launch_one(const FwdArgs &a, hipStream_t s) {
+  const int per = FD ? a.spw : pd_per<UT, PREC>();
+  const int tasks = (a.W + per - 1) / per;
+  hipLaunchKernelGGL((eq_forward_kernel<UT, PREC, FD>), dim3(tasks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int UT, bool FD>
 static hipError_t launch_prec(const FwdArgs &a, int prec, hipStream_t s) {
-  const int nsys = 64 / UT;
-  const int tasks = FD ? (a.W + a.spw - 1) / a.spw : (a.W + nsys - 1) / nsys;
-  const dim3 grid(tasks), block(64);
   switch (prec) {
-    case PREC_FP32: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_FP32, FD>), grid, block, 0, s, a); break;
-    case PREC_BF16: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_BF16, FD>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((eq_forward_kernel<UT, PREC_BF16X3, FD>), grid, block, 0, s, a); break;
+    case PREC_FP32: return launch_one<UT, PREC_FP32, FD>(a, s);
+    case PREC_BF16: return launch_one<UT, PREC_BF16, FD>(a, s);
+    case PREC_BF16X3: return launch_one<UT, PREC_BF16X3, FD>(a, s);
+    default: return launch_one<UT, PREC_BF16X3_NR, FD>(a, s);
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_forward(const FwdArgs &a, bool fd, int prec, hipStream_t s) {

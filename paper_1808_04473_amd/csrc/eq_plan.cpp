@@ -256,7 +256,7 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const 
   *out = nullptr;
   if (nsys < 1 || !desc || !sizes || nsizes < 1) return EQ_EINVAL;
   if (fd != 0 && fd != 1) return EQ_EINVAL;
-  if (precision < EQ_FP32 || precision > EQ_BF16X3_REFINE) return EQ_EINVAL;
+  if (precision < EQ_FP32 || precision > EQ_BF16X3) return EQ_EINVAL;
   if (!isfinite(es) || !(es > 0.f)) return EQ_EINVAL;
   eq_plan *p = new eq_plan();
   p->fd = fd;

@@ -36,7 +36,7 @@ __device__ __forceinline__ void ragged_pd(const RaggedArgs &a, const RTask &task
   const bool live = sme < n;
   LocalSolve<UT> r;
   local_solve<UT>(r, sm, sme, i, U);
-  if constexpr (PREC != PREC_FP32)
+  if constexpr (refines(PREC))
     refine_round<UT>(r, sm, n, U, [&](int s) { return a.sys[sysk(s)].rho; }, seg, live);
   const float kappa = r.norm1 * gsum<UT>(i < U ? r.d : 0.f);
   const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
@@ -90,7 +90,7 @@ __device__ __forceinline__ void ragged_fd(const RaggedArgs &a, const RTask &task
     const bool live = sme < n;
     LocalSolve<UT> r;
     local_solve<UT>(r, sm, sme, i, U);
-    if constexpr (PREC != PREC_FP32)
+    if constexpr (refines(PREC))
       refine_round<UT>(r, sm, n, U, [&](int) { return d.rho; }, seg, live);
     const float kappa = r.norm1 * gsum<UT>(i < U ? r.d : 0.f);
     const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
@@ -171,7 +171,8 @@ hipError_t launch_ragged(const RaggedArgs &a, bool fd, int prec, int grid, hipSt
   switch (prec) {
     case PREC_FP32: EQ_RAGGED_LAUNCH(PREC_FP32) break;
     case PREC_BF16: EQ_RAGGED_LAUNCH(PREC_BF16) break;
-    default: EQ_RAGGED_LAUNCH(PREC_BF16X3) break;
+    case PREC_BF16X3: EQ_RAGGED_LAUNCH(PREC_BF16X3) break;
+    default: EQ_RAGGED_LAUNCH(PREC_BF16X3_NR) break;
   }
 #undef EQ_RAGGED_LAUNCH
   return hipGetLastError();

@@ -34,7 +34,7 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int
   for (int k = 0; k < UT; ++k) {
     r.f.a[k] = sm.A[sme][i][k];
     bad |= !finite2(r.f.a[k]);
-    rowsum += sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
+    rowsum += __builtin_amdgcn_sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
   }
   const float2 m = sm.M[sme][i];
   bad |= !finite2(m);

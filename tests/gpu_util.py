@@ -40,5 +40,5 @@ def sinr_db_empirical(z, s):
 
 
 # gates (error on the equalised symbols; SINR)
-TOL_Z = {"fp32": 1e-4, "bf16": 2e-4, "bf16x3": 2e-4}
+TOL_Z = {"fp32": 1e-4, "bf16_refine": 2e-4, "bf16x3_refine": 2e-4, "bf16x3": 1e-4}
 TOL_DB = 0.05

@@ -70,7 +70,7 @@ def _call_fd(lib, prob, nu=None, H=A, y=A, z=A, ws=A, wsb=1 << 12):
     (dict(n0=float("inf")), EINVAL), (dict(es=0.0), EINVAL), (dict(es=float("nan")), EINVAL),
     (dict(off=(0, 4, 7)), EINVAL), (dict(off=(1, 4, 8)), EINVAL), (dict(off=(0, 4, 4, 8)), EINVAL),
     (dict(off=(0, 5, 4, 8)), EINVAL), (dict(U=0), EINVAL), (dict(U=33), ENOTSUP),
-    (dict(W=-1), EINVAL), (dict(B=0, off=(0,)), EINVAL), (dict(prec=7), EINVAL),
+    (dict(W=-1), EINVAL), (dict(B=0, off=(0,)), EINVAL), (dict(prec=4), EINVAL), (dict(prec=7), EINVAL),
     (dict(prec=-1), EINVAL),
 ])
 def test_invalid_problem_rejected(lib, kw, expect):
