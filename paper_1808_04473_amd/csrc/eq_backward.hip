@@ -106,7 +106,7 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
 #pragma unroll
       for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[0][k][col];
     }
-    stream_blocks<UT>(
+    stream_blocks<UT, kLoadLast>(
         nvalid, U, seg,
         [&](const Slot &b) {
           float2 *gHw = a.gH ? a.gH + (b.Hw - a.H) : nullptr;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void gram_round(const BwdArgs &a, BSmem<UT> &sm, int 
                                            const Seg &seg) {
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
-  gram_stream<UT, PREC_FP32>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+  gram_stream<UT, PREC_FP32, kLoadKeep>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
     store_gram<UT>(sm.r.A[s], acc, a.rho);
     if (lane < UT) sm.r.M[s][lane] = mf;
   });

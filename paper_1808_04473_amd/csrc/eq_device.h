@@ -82,6 +82,26 @@ __device__ __forceinline__ float2 gbcast2(float2 v) {
   return make_float2(gbcast<UT, K>(v.x), gbcast<UT, K>(v.y));
 }
 
+// acc += (NEG ? -1 : 1) * src[lane K of this lane's DPP row] * b: one VOP2
+// FMAC whose src0 comes through a DPP row broadcast (a group of 16 lanes is
+// a DPP row).  Written as inline assembly because the compiler folds DPP
+// movs into adds but not into FMACs.  Each instruction carries its own wait
+// states: a DPP source written by a VALU needs two before it is read; NOP = 4
+// also covers a VALU write of EXEC (five), used once at the head of a step.
+#define EQ_FMAC_ROWBCAST(PRE, NEGS)                                                          \
+  asm volatile(PRE "\n\tv_fmac_f32_dpp %0, " NEGS "%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" \
+               : "+v"(acc)                                                                     \
+               : "v"(src), "v"(b), "n"(K))
+template <int K, bool NEG, int NOP>
+__device__ __forceinline__ void fmac_rowbcast(float &acc, float src, float b) {
+  static_assert(NOP == 1 || NOP == 4, "wait states");
+  if constexpr (NEG && NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4", "-");
+  else if constexpr (NEG) EQ_FMAC_ROWBCAST("s_nop 1", "-");
+  else if constexpr (NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4", "");
+  else EQ_FMAC_ROWBCAST("s_nop 1", "");
+}
+#undef EQ_FMAC_ROWBCAST
+
 // Sum over the 16 lanes of a DPP row; every lane receives the sum.
 __device__ __forceinline__ float row16_sum(float v) {
 #ifndef EQ_NO_DPP
@@ -204,9 +224,16 @@ struct SysRef {
 constexpr int kBufFlags = 0x00020000;  // raw 32-bit buffer, gfx9 format bits
 constexpr unsigned kOutOfRange = 0x80000000u;
 
+// Cache policy of a stream's loads: the last read of these bytes uses the
+// nontemporal policy (they are not kept in L2 / Infinity Cache); a read that
+// a later pass of the same wave repeats uses the default policy.
+constexpr int kLoadKeep = 0;
+constexpr int kLoadLast = 2;  // NT
+
+template <int AUX>
 __device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off) {
   typedef float f2v __attribute__((ext_vector_type(2)));
-  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
   return make_float2(v.x, v.y);
 }
 
@@ -228,7 +255,7 @@ __device__ __forceinline__ LaneOff<UT> lane_offsets(int U) {
   return o;
 }
 
-template <int UT>
+template <int UT, int AUX>
 __device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const float2 *__restrict__ Hw,
                                           const float2 *__restrict__ yw, int U, int rb, int r0,
                                           int r1) {
@@ -240,8 +267,8 @@ __device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const 
   const unsigned rowb = (unsigned)((rb - r0) * U * 8);
   const unsigned step = (unsigned)(RPS * U * 8);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2(rh, lo.h + rowb + e * step);
-  b.yl = buf_ld2(ry, lo.y + (unsigned)((rb - r0) * 8));
+  for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2<AUX>(rh, lo.h + rowb + e * step);
+  b.yl = buf_ld2<AUX>(ry, lo.y + (unsigned)((rb - r0) * 8));
   b.Hw = Hw;
   b.yw = yw;
   b.rb = rb;
@@ -267,7 +294,7 @@ __device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
 // the loads of the next two blocks in flight while body(slot) consumes the
 // current one; done(slot) follows the last block of each system, while the
 // next blocks' loads are still in flight.
-template <int UT, class Gen, class Body, class Done>
+template <int UT, int AUX, class Gen, class Body, class Done>
 __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done) {
   constexpr int RPB = 8 * (64 / UT);
   SysRef cur;
@@ -280,7 +307,7 @@ __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done
   // same on every path and the compiler can wait for one block at a time.
   auto issue = [&](Slot &sl) -> bool {
     const bool valid = more;
-    load_slot<UT>(sl, lo, cur.Hw, cur.yw, U, crb, cur.r0, cur.r1);
+    load_slot<UT, AUX>(sl, lo, cur.Hw, cur.yw, U, crb, cur.r0, cur.r1);
     sl.s = cur.s;
     sl.tk = cur.tk;
     sl.last = crb + RPB >= cur.r1;
@@ -375,7 +402,7 @@ __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done
 
 // Fixed list of systems 0..ns-1 described by seg(s, Hw, yw, r0, r1);
 // done(s) follows the last block of system s.
-template <int UT, class Seg, class Body, class Done>
+template <int UT, int AUX, class Seg, class Body, class Done>
 __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body, Done done) {
   int next = 0;
   auto gen = [&](SysRef &r) -> bool {
@@ -385,7 +412,7 @@ __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body,
     r.s = next++;
     return true;
   };
-  stream_gen<UT>(U, gen, body, [&](const Slot &sl) { done(sl.s); });
+  stream_gen<UT, AUX>(U, gen, body, [&](const Slot &sl) { done(sl.s); });
 }
 
 // ---------------------------------------------------------------- Gram + matched filter
@@ -445,12 +472,13 @@ __device__ __forceinline__ void gram_blk(const Slot &sl, int U, Acc<UT> &acc, fl
 
 // Gram + matched filter of systems 0..ns-1; done(s, acc, mf) receives each
 // system's accumulators and its matched filter (reduced over a column).
-template <int UT, int PREC, class Seg, class Done>
+// AUX is the loads' cache policy (kLoadLast unless a later pass re-reads H).
+template <int UT, int PREC, int AUX, class Seg, class Done>
 __device__ __forceinline__ void gram_stream(int ns, int U, Seg seg, Done done) {
   Acc<UT> acc;
   acc_zero<UT>(acc);
   float mfx = 0.f, mfy = 0.f;
-  stream_blocks<UT>(
+  stream_blocks<UT, AUX>(
       ns, U, seg, [&](const Slot &b) { gram_blk<UT, PREC>(b, U, acc, mfx, mfy); },
       [&](int s) {
         done(s, acc, make_float2(colsum<UT>(mfx), colsum<UT>(mfy)));
@@ -467,7 +495,7 @@ template <int UT, class Seg, class Zc, class Done>
 __device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, Done done) {
   float nx = 0.f, ny = 0.f;
   float2 zc = zcf(0);
-  stream_blocks<UT>(
+  stream_blocks<UT, kLoadLast>(
       ns, U, seg,
       [&](const Slot &b) {
 #pragma unroll
@@ -566,15 +594,34 @@ __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
     if (i < j) lij = make_float2(0.f, 0.f);
     f.a[j] = lij;
     const float2 lm = (i > j) ? lij : make_float2(0.f, 0.f);
-    sfor<UT>([&](auto K) {
-      constexpr int k = K;
-      if constexpr (k > j) {
-        const float2 lkj = gbcast2<UT, k>(lij);
-        // a_ik -= l_ij * conj(l_kj)
-        f.a[k].x -= lm.x * lkj.x + lm.y * lkj.y;
-        f.a[k].y -= lm.y * lkj.x - lm.x * lkj.y;
-      }
-    });
+    // a_ik -= l_ij * conj(l_kj), with l_kj broadcast from lane k
+    if constexpr (UT == 16) {
+      // real part of l_kj for every k, then the imaginary part, so that no
+      // instruction reads an accumulator its predecessor wrote
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k > j) {
+          fmac_rowbcast<k, true, k == j + 1 ? 4 : 1>(f.a[k].x, lij.x, lm.x);
+          fmac_rowbcast<k, true, 1>(f.a[k].y, lij.x, lm.y);
+        }
+      });
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k > j) {
+          fmac_rowbcast<k, true, 1>(f.a[k].x, lij.y, lm.y);
+          fmac_rowbcast<k, false, 1>(f.a[k].y, lij.y, lm.x);
+        }
+      });
+    } else {
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k > j) {
+          const float2 lkj = gbcast2<UT, k>(lij);
+          f.a[k].x -= lm.x * lkj.x + lm.y * lkj.y;
+          f.a[k].y -= lm.y * lkj.x - lm.x * lkj.y;
+        }
+      });
+    }
     step_fence();
   });
   return fail;
@@ -582,31 +629,60 @@ __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
 
 // Lane u computes column u of X = L^{-1}:
 //   X_ju = (delta_ju - sum_{k<j} L_jk X_ku) / L_jj.
-// Row j of L is broadcast from lane j.  Each step's broadcast sources are
-// tied to the previous step's result, so the compiler neither hoists all
-// broadcasts to the top (hundreds of live values) nor merges them with the
-// identical broadcasts of the factorisation.
+// UT = 16 runs it right-looking: once X_ju is final, every later row i
+// subtracts L_ij X_ju (L_ij broadcast from lane i), so each step has 15 - j
+// independent accumulators instead of one long chain.  UT = 32 runs the dot
+// products; each step's broadcast sources are tied to the previous step's
+// result, so the compiler neither hoists all broadcasts to the top (hundreds
+// of live values) nor merges them with the identical broadcasts of the
+// factorisation.
 template <int UT>
 __device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
-  float dep = 0.f;
-  sfor<UT>([&](auto J) {
-    constexpr int j = J;
-    float ax = (u == j) ? 1.f : 0.f, ay = 0.f;
-    sfor<UT>([&](auto K) {
-      constexpr int k = K;
-      if constexpr (k < j) {
-        float2 src = f.a[k];
-        asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
-        const float2 ljk = gbcast2<UT, j>(src);
-        ax -= ljk.x * f.x[k].x - ljk.y * f.x[k].y;
-        ay -= ljk.x * f.x[k].y + ljk.y * f.x[k].x;
-      }
+  if constexpr (UT == 16) {
+#pragma unroll
+    for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+    sfor<UT>([&](auto J) {
+      constexpr int j = J;
+      const float invj = gbcast<UT, j>(f.dinv);
+      f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
+      // x_i -= L_ij x_j: real part of L_ij for every i, then the imaginary part
+      sfor<UT>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > j) {
+          fmac_rowbcast<i, true, i == j + 1 ? 4 : 1>(f.x[i].x, f.a[j].x, f.x[j].x);
+          fmac_rowbcast<i, true, 1>(f.x[i].y, f.a[j].x, f.x[j].y);
+        }
+      });
+      sfor<UT>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > j) {
+          fmac_rowbcast<i, false, 1>(f.x[i].x, f.a[j].y, f.x[j].y);
+          fmac_rowbcast<i, true, 1>(f.x[i].y, f.a[j].y, f.x[j].x);
+        }
+      });
+      step_fence();
     });
-    const float invj = gbcast<UT, j>(f.dinv);
-    f.x[j] = make_float2(ax * invj, ay * invj);
-    dep = f.x[j].x;
-    step_fence();
-  });
+  } else {
+    float dep = 0.f;
+    sfor<UT>([&](auto J) {
+      constexpr int j = J;
+      float ax = (u == j) ? 1.f : 0.f, ay = 0.f;
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k < j) {
+          float2 src = f.a[k];
+          asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
+          const float2 ljk = gbcast2<UT, j>(src);
+          ax -= ljk.x * f.x[k].x - ljk.y * f.x[k].y;
+          ay -= ljk.x * f.x[k].y + ljk.y * f.x[k].x;
+        }
+      });
+      const float invj = gbcast<UT, j>(f.dinv);
+      f.x[j] = make_float2(ax * invj, ay * invj);
+      dep = f.x[j].x;
+      step_fence();
+    });
+  }
 }
 
 // t = L^{-1} b by forward substitution; lane i holds b_i on entry, t_i on exit.

@@ -62,7 +62,7 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm
 
   // ---- Gram + matched filter of the round's subcarriers (all clusters
   //      accumulate into one G and one y^MRC: the adder tree of eq. (fullMRC))
-  gram_stream<UT, PREC>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+  gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
     store_gram<UT>(sm.A[s], acc, a.rho);
     if (lane < UT) sm.M[s][lane] = mf;
   });
@@ -125,7 +125,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
       r1 = a.off[c + 1];
     };
     // ---- local Gram + MRC of the clusters of this round
-    gram_stream<UT, PREC>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+    gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
       store_gram<UT>(sm.A[s], acc, a.rho);
       if (lane < UT) sm.M[s][lane] = mf;
     });

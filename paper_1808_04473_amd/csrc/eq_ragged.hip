@@ -24,7 +24,7 @@ __device__ __forceinline__ void ragged_pd(const RaggedArgs &a, const RTask &task
     r0 = 0;
     r1 = d.B;
   };
-  gram_stream<UT, PREC>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+  gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
     store_gram<UT>(sm.A[s], acc, a.sys[sysk(s)].rho);
     if (lane < UT) sm.M[s][lane] = mf;
   });
@@ -78,7 +78,7 @@ __device__ __forceinline__ void ragged_fd(const RaggedArgs &a, const RTask &task
       r0 = a.offs[d.off_first + base + s];
       r1 = a.offs[d.off_first + base + s + 1];
     };
-    gram_stream<UT, PREC>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
+    gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
       store_gram<UT>(sm.A[s], acc, d.rho);
       if (lane < UT) sm.M[s][lane] = mf;
     });
