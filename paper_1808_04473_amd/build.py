@@ -5,7 +5,9 @@
 Every translation unit is compiled to an object file under
 paper_1808_04473_amd/_build/ (in parallel), then linked into
 paper_1808_04473_amd/libdbpeq.so.  Packed FP32 VALU instructions are disabled
-for all device code.
+for all device code.  The device assembly of each HIP file is kept
+(-save-temps) and checked for DPP read hazards of the hand-written DPP
+instructions (isa_check) before the library is linked.
 """
 from __future__ import annotations
 
@@ -40,11 +42,19 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
+def device_asm(src: str) -> str:
+    """Device assembly that -save-temps=obj leaves for a HIP source."""
+    stem = os.path.splitext(os.path.basename(src))[0]
+    return os.path.join(BUILD, f"{stem}-hip-amdgcn-amd-amdhsa-{ARCH}.s")
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
+    else:
+        cmd.insert(1, "-save-temps=obj")
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,6 +69,13 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    from . import isa_check
+    errs = []
+    for src in srcs:
+        if src.endswith(".hip"):
+            errs += isa_check.check_file(device_asm(src))
+    if errs:
+        raise RuntimeError("DPP hazards in the device assembly:\n" + "\n".join(errs[:20]))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

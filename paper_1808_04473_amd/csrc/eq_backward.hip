@@ -90,7 +90,7 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
       step_fence();
     });
 #pragma unroll
-    for (int k = 0; k < UT; ++k) sm.r.A[sme][k][i] = q[k];
+    for (int k = 0; k < UT; ++k) lds_el<UT>(sm.r.A[sme], k, i) = q[k];
   }
   sm.r.M[sme][i] = r.z;
   sm.L[sme][i] = lam;
@@ -104,7 +104,7 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
     float2 qc[UT];
     if (use_q) {
 #pragma unroll
-      for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[0][k][col];
+      for (int k = 0; k < UT; ++k) qc[k] = lds_el<UT>(sm.r.A[0], k, col);
     }
     stream_blocks<UT, kLoadLast>(
         nvalid, U, seg,
@@ -147,7 +147,7 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
             lc = sm.L[s + 1][col];
             if (use_q) {
 #pragma unroll
-              for (int k = 0; k < UT; ++k) qc[k] = sm.r.A[s + 1][k][col];
+              for (int k = 0; k < UT; ++k) qc[k] = lds_el<UT>(sm.r.A[s + 1], k, col);
             }
           }
         });

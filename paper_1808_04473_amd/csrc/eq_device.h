@@ -16,7 +16,8 @@
 //    L), the inverse factor X = L^{-1} by columns (lane u owns column u), so
 //    diag(A^{-1})_u = sum_j |X_ju|^2 and z = X^H (L^{-1} m) need no
 //    cross-lane reduction.  Values move between lanes of a group by
-//    broadcasting one lane (DPP row broadcast or v_readlane).
+//    broadcasting one lane: a DPP row broadcast, after a v_permlane16_swap
+//    for 32-lane groups, fused into the FMAC that consumes it.
 #pragma once
 #include <utility>
 
@@ -38,7 +39,15 @@ __device__ __forceinline__ void sfor(F &&f) {
   sfor_impl(std::make_integer_sequence<int, N>{}, f);
 }
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+// Lane index within the wave.  Opaque to the optimiser: otherwise every
+// lane-dependent value (masks, offsets, selects) is computed once and kept
+// live across the whole kernel, which costs tens of registers; recomputing
+// it is one VALU instruction.
+__device__ __forceinline__ int lane_id() {
+  int l = threadIdx.x & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
 
 // ---------------------------------------------------------------- cross-lane primitives
 // DPP controls (GCN/CDNA data-parallel primitives).
@@ -53,29 +62,34 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+// Broadcast source of a value v for groups of UT lanes.  A group of 16 lanes
+// is one DPP row, so lane K of it is DPP row_newbcast:K of v itself.  A group
+// of 32 lanes spans two rows: v_permlane16_swap(v, v) yields `lo`, in which
+// the group's first row fills both of its rows, and `hi`, with the second
+// row; lane K of the group is then row_newbcast:(K % 16) of lo (K < 16) or
+// hi.  One swap serves every K, so a step that broadcasts the same register
+// from many lanes pays for it once.
+struct BSrc {
+  float lo, hi;
+};
+template <int UT>
+__device__ __forceinline__ BSrc bsrc(float v) {
+  if constexpr (UT == 16) {
+    return {v, v};
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+  }
+}
+template <int K>
+__device__ __forceinline__ float bpick(const BSrc &b) {
+  return K < 16 ? b.lo : b.hi;
+}
+
 // Value of lane K of this lane's group of UT lanes.
 template <int UT, int K>
 __device__ __forceinline__ float gbcast(float v) {
-#ifndef EQ_NO_DPP
-  if constexpr (UT == 16) {
-    return dpp<DPP_ROW_NEWBCAST + K>(v);
-  } else
-#endif
-  {
-    // one v_readlane per group, then select by group
-    if constexpr (UT == 16) {
-      const float v0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), K));
-      const float v1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 + K));
-      const float v2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + K));
-      const float v3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48 + K));
-      const int g = lane_id() >> 4;
-      return g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : v3;
-    } else {
-      const float v0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), K));
-      const float v1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + K));
-      return lane_id() < 32 ? v0 : v1;
-    }
-  }
+  return dpp<DPP_ROW_NEWBCAST + K % 16>(bpick<K>(bsrc<UT>(v)));
 }
 template <int UT, int K>
 __device__ __forceinline__ float2 gbcast2(float2 v) {
@@ -83,22 +97,25 @@ __device__ __forceinline__ float2 gbcast2(float2 v) {
 }
 
 // acc += (NEG ? -1 : 1) * src[lane K of this lane's DPP row] * b: one VOP2
-// FMAC whose src0 comes through a DPP row broadcast (a group of 16 lanes is
-// a DPP row).  Written as inline assembly because the compiler folds DPP
-// movs into adds but not into FMACs.  Each instruction carries its own wait
-// states: a DPP source written by a VALU needs two before it is read; NOP = 4
-// also covers a VALU write of EXEC (five), used once at the head of a step.
+// FMAC whose src0 comes through a DPP row broadcast (src is a BSrc half, so
+// that K = group lane % 16).  Written as inline assembly because the
+// compiler folds DPP movs into adds but not into FMACs.  The hardware needs
+// two wait states between a VALU write of the DPP source and the read (five
+// after a VALU write of EXEC); the compiler does not see the DPP operand of
+// inline assembly, so NOP = 4 puts an s_nop 4 at the head of each group of
+// these instructions, whose sources are written before the group and not
+// inside it.  The build checks the generated assembly for these hazards.
 #define EQ_FMAC_ROWBCAST(PRE, NEGS)                                                          \
-  asm volatile(PRE "\n\tv_fmac_f32_dpp %0, " NEGS "%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" \
+  asm volatile(PRE "v_fmac_f32_dpp %0, " NEGS "%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" \
                : "+v"(acc)                                                                     \
                : "v"(src), "v"(b), "n"(K))
 template <int K, bool NEG, int NOP>
 __device__ __forceinline__ void fmac_rowbcast(float &acc, float src, float b) {
-  static_assert(NOP == 1 || NOP == 4, "wait states");
-  if constexpr (NEG && NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4", "-");
-  else if constexpr (NEG) EQ_FMAC_ROWBCAST("s_nop 1", "-");
-  else if constexpr (NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4", "");
-  else EQ_FMAC_ROWBCAST("s_nop 1", "");
+  static_assert(NOP == 0 || NOP == 4, "wait states");
+  if constexpr (NEG && NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4\n\t", "-");
+  else if constexpr (NEG) EQ_FMAC_ROWBCAST("", "-");
+  else if constexpr (NOP == 4) EQ_FMAC_ROWBCAST("s_nop 4\n\t", "");
+  else EQ_FMAC_ROWBCAST("", "");
 }
 #undef EQ_FMAC_ROWBCAST
 
@@ -205,6 +222,7 @@ struct Slot {
   const float2 *yw;
   int s, rb, r1;  // s: system index within its task
   int tk;         // task the system belongs to
+  int g;          // row group of this lane (lane / UT)
   bool last;
 };
 
@@ -242,6 +260,7 @@ template <int UT>
 struct LaneOff {
   unsigned h;  // (g * U + col) * 8, or out of range for padded columns
   unsigned y;  // lane * 8 for the lanes that load y, else out of range
+  int g;       // row group lane / UT
 };
 
 template <int UT>
@@ -252,6 +271,7 @@ __device__ __forceinline__ LaneOff<UT> lane_offsets(int U) {
   LaneOff<UT> o;
   o.h = col < U ? (unsigned)((g * U + col) * 8) : kOutOfRange;
   o.y = lane < RPB ? (unsigned)(lane * 8) : kOutOfRange;
+  o.g = g;
   return o;
 }
 
@@ -269,6 +289,7 @@ __device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const 
 #pragma unroll
   for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2<AUX>(rh, lo.h + rowb + e * step);
   b.yl = buf_ld2<AUX>(ry, lo.y + (unsigned)((rb - r0) * 8));
+  b.g = lo.g;
   b.Hw = Hw;
   b.yw = yw;
   b.rb = rb;
@@ -285,7 +306,7 @@ __device__ __forceinline__ float2 slot_h(const Slot &b, int e, int) {
 template <int UT>
 __device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
   constexpr int RPS = 64 / UT;
-  const int src = e * RPS + lane_id() / UT;
+  const int src = e * RPS + b.g;
   return make_float2(__shfl(b.yl.x, src), __shfl(b.yl.y, src));
 }
 
@@ -521,18 +542,26 @@ __device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, 
       });
 }
 
+// Element (i, k) of a UT x UT matrix in LDS.  Rows are not padded: column k
+// of row i is stored at k ^ i, so that the lanes of a group that read one
+// row, or one column, touch UT different banks.
+template <int UT>
+__device__ __forceinline__ float2 &lds_el(float2 (*As)[UT], int i, int k) {
+  return As[i][k ^ i];
+}
+
 // Writes G + rho I of one system from the MFMA accumulators into LDS
-// (full Hermitian matrix, row stride UT + 1):
+// (full Hermitian matrix, swizzled rows):
 //   Re G = Hr^T Hr + Hi^T Hi,   Im G[i][j] = (Hr^T Hi)[i][j] - (Hr^T Hi)[j][i].
 template <int UT>
-__device__ __forceinline__ void store_gram(float2 (*As)[UT + 1], const Acc<UT> &acc, float rho) {
+__device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc, float rho) {
   constexpr int NR = UT == 16 ? 4 : 16;
   const int lane = lane_id();
   sfor<NR>([&](auto R) {
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    As[i][j] = make_float2(0.f, acc.ri[r]);
+    lds_el<UT>(As, i, j) = make_float2(0.f, acc.ri[r]);
   });
   __syncthreads();
   float im[NR];
@@ -540,22 +569,22 @@ __device__ __forceinline__ void store_gram(float2 (*As)[UT + 1], const Acc<UT> &
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    im[r] = acc.ri[r] - As[j][i].y;
+    im[r] = acc.ri[r] - lds_el<UT>(As, j, i).y;
   });
   __syncthreads();
   sfor<NR>([&](auto R) {
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    As[i][j] = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? rho : 0.f), im[r]);
+    lds_el<UT>(As, i, j) = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? rho : 0.f), im[r]);
   });
 }
 
 template <int UT>
-__device__ __forceinline__ void store_identity(float2 (*As)[UT + 1]) {
+__device__ __forceinline__ void store_identity(float2 (*As)[UT]) {
   for (int idx = lane_id(); idx < UT * UT; idx += 64) {
     const int i = idx / UT, j = idx % UT;
-    As[i][j] = make_float2(i == j ? 1.f : 0.f, 0.f);
+    lds_el<UT>(As, i, j) = make_float2(i == j ? 1.f : 0.f, 0.f);
   }
 }
 
@@ -569,6 +598,14 @@ __device__ __forceinline__ void step_fence() { __builtin_amdgcn_sched_barrier(0)
 // and reusing those would keep every broadcast of the factorisation live.
 __device__ __forceinline__ void opaque(float2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
+// The same for a lane index: each phase of the solve compares it with the
+// step number, and sharing those lane masks between phases would keep dozens
+// of 64-bit masks live in scalar registers.
+__device__ __forceinline__ int opaque_idx(int i) {
+  asm volatile("" : "+v"(i));
+  return i;
+}
+
 template <int UT>
 struct Factor {
   float2 a[UT];   // row i of L (entries j <= i), lane i of the group
@@ -580,6 +617,7 @@ struct Factor {
 // Returns 0, or j+1 for the first pivot j that is not positive (or NaN).
 template <int UT>
 __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
+  i = opaque_idx(i);
   int fail = 0;
   sfor<UT>([&](auto J) {
     constexpr int j = J;
@@ -594,100 +632,67 @@ __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
     if (i < j) lij = make_float2(0.f, 0.f);
     f.a[j] = lij;
     const float2 lm = (i > j) ? lij : make_float2(0.f, 0.f);
-    // a_ik -= l_ij * conj(l_kj), with l_kj broadcast from lane k
-    if constexpr (UT == 16) {
-      // real part of l_kj for every k, then the imaginary part, so that no
-      // instruction reads an accumulator its predecessor wrote
-      sfor<UT>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (k > j) {
-          fmac_rowbcast<k, true, k == j + 1 ? 4 : 1>(f.a[k].x, lij.x, lm.x);
-          fmac_rowbcast<k, true, 1>(f.a[k].y, lij.x, lm.y);
-        }
-      });
-      sfor<UT>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (k > j) {
-          fmac_rowbcast<k, true, 1>(f.a[k].x, lij.y, lm.y);
-          fmac_rowbcast<k, false, 1>(f.a[k].y, lij.y, lm.x);
-        }
-      });
-    } else {
-      sfor<UT>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (k > j) {
-          const float2 lkj = gbcast2<UT, k>(lij);
-          f.a[k].x -= lm.x * lkj.x + lm.y * lkj.y;
-          f.a[k].y -= lm.y * lkj.x - lm.x * lkj.y;
-        }
-      });
-    }
+    // a_ik -= l_ij * conj(l_kj), with l_kj broadcast from lane k: the real
+    // part of l_kj for every k, then the imaginary part, so that no
+    // instruction reads an accumulator its predecessor wrote
+    const BSrc bx = bsrc<UT>(lij.x), by = bsrc<UT>(lij.y);
+    sfor<UT>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (k > j) {
+        fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(bx), lm.x);
+        fmac_rowbcast<k % 16, true, 0>(f.a[k].y, bpick<k>(bx), lm.y);
+      }
+    });
+    sfor<UT>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (k > j) {
+        fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(by), lm.y);
+        fmac_rowbcast<k % 16, false, 0>(f.a[k].y, bpick<k>(by), lm.x);
+      }
+    });
     step_fence();
   });
   return fail;
 }
 
 // Lane u computes column u of X = L^{-1}:
-//   X_ju = (delta_ju - sum_{k<j} L_jk X_ku) / L_jj.
-// UT = 16 runs it right-looking: once X_ju is final, every later row i
-// subtracts L_ij X_ju (L_ij broadcast from lane i), so each step has 15 - j
-// independent accumulators instead of one long chain.  UT = 32 runs the dot
-// products; each step's broadcast sources are tied to the previous step's
-// result, so the compiler neither hoists all broadcasts to the top (hundreds
-// of live values) nor merges them with the identical broadcasts of the
-// factorisation.
+//   X_ju = (delta_ju - sum_{k<j} L_jk X_ku) / L_jj,
+// right-looking: once X_ju is final, every later row i subtracts L_ij X_ju
+// (L_ij broadcast from lane i), so each step has UT - 1 - j independent
+// accumulators instead of one long chain.
 template <int UT>
 __device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
-  if constexpr (UT == 16) {
+  u = opaque_idx(u);
 #pragma unroll
-    for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
-    sfor<UT>([&](auto J) {
-      constexpr int j = J;
-      const float invj = gbcast<UT, j>(f.dinv);
-      f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
-      // x_i -= L_ij x_j: real part of L_ij for every i, then the imaginary part
-      sfor<UT>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i > j) {
-          fmac_rowbcast<i, true, i == j + 1 ? 4 : 1>(f.x[i].x, f.a[j].x, f.x[j].x);
-          fmac_rowbcast<i, true, 1>(f.x[i].y, f.a[j].x, f.x[j].y);
-        }
-      });
-      sfor<UT>([&](auto I) {
-        constexpr int i = I;
-        if constexpr (i > j) {
-          fmac_rowbcast<i, false, 1>(f.x[i].x, f.a[j].y, f.x[j].y);
-          fmac_rowbcast<i, true, 1>(f.x[i].y, f.a[j].y, f.x[j].x);
-        }
-      });
-      step_fence();
+  for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    const float invj = gbcast<UT, j>(f.dinv);
+    f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
+    // x_i -= L_ij x_j: real part of L_ij for every i, then the imaginary part
+    const BSrc bx = bsrc<UT>(f.a[j].x), by = bsrc<UT>(f.a[j].y);
+    sfor<UT>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (i > j) {
+        fmac_rowbcast<i % 16, true, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(bx), f.x[j].x);
+        fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(bx), f.x[j].y);
+      }
     });
-  } else {
-    float dep = 0.f;
-    sfor<UT>([&](auto J) {
-      constexpr int j = J;
-      float ax = (u == j) ? 1.f : 0.f, ay = 0.f;
-      sfor<UT>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (k < j) {
-          float2 src = f.a[k];
-          asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
-          const float2 ljk = gbcast2<UT, j>(src);
-          ax -= ljk.x * f.x[k].x - ljk.y * f.x[k].y;
-          ay -= ljk.x * f.x[k].y + ljk.y * f.x[k].x;
-        }
-      });
-      const float invj = gbcast<UT, j>(f.dinv);
-      f.x[j] = make_float2(ax * invj, ay * invj);
-      dep = f.x[j].x;
-      step_fence();
+    sfor<UT>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (i > j) {
+        fmac_rowbcast<i % 16, false, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(by), f.x[j].y);
+        fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(by), f.x[j].x);
+      }
     });
-  }
+    step_fence();
+  });
 }
 
 // t = L^{-1} b by forward substitution; lane i holds b_i on entry, t_i on exit.
 template <int UT>
 __device__ __forceinline__ float2 fwd_subst(const Factor<UT> &f, int i, float2 b) {
+  i = opaque_idx(i);
   float2 t = b;
   sfor<UT>([&](auto J) {
     constexpr int j = J;

@@ -34,26 +34,26 @@ constexpr int pd_per() {
   return refines(PREC) && UT == 16 ? 2 : 64 / UT;
 }
 
-// Occupancy target: 4 waves per SIMD (128 VGPRs) for the streaming PD forms,
-// 3 (168 VGPRs, no spills) for FD and for the refining forms.
+// Occupancy target.  UT = 16: 4 waves per SIMD (128 VGPRs) for the
+// one-pass forms; 3 (168 VGPRs) for the refining forms, which hold a factor
+// across the residual pass, and for FD with the split-BF16 Gram, whose
+// operand splits spill at 128.  UT = 32: 2 (256 VGPRs); the factor and the
+// inverse columns alone take 129.
 template <int UT, int PREC, bool FD>
 constexpr int waves_target() {
-  return (FD || refines(PREC)) ? 3 : EQ_WAVES_PER_EU;
+  if (UT == 32) return 2;
+  return (refines(PREC) || (FD && PREC == PREC_BF16X3_NR)) ? 3 : EQ_WAVES_PER_EU;
 }
 
 template <int UT, int PREC>
-__device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm) {
+__device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, Smem<UT> &sm) {
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
   const int sme = lane / UT;
   const int i = lane % UT;
   const size_t HB = (size_t)a.B * a.U;
-  // refining forms take half a round of subcarriers per task: the residual
-  // pass then re-reads H soon enough to find it in the Infinity Cache
-  constexpr int PER = pd_per<UT, PREC>();
-  const int nvalid = min(PER, a.W - task * PER);
   auto seg = [&](int s, const float2 *&Hw, const float2 *&yw, int &r0, int &r1) {
-    const size_t w = (size_t)task * PER + s;
+    const size_t w = (size_t)w0 + s;
     Hw = a.H + w * HB;
     yw = a.y + w * a.B;
     r0 = 0;
@@ -73,7 +73,7 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm
   __syncthreads();
 
   // ---- factor and solve: group sme, row/column i
-  const int w = task * PER + sme;
+  const int w = w0 + sme;
   const bool live = sme < nvalid;
   LocalSolve<UT> r;
   local_solve<UT>(r, sm, sme, i, a.U);
@@ -95,16 +95,15 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int task, Smem<UT> &sm
 }
 
 template <int UT, int PREC>
-__device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm) {
+__device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, Smem<UT> &sm) {
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
   const int sme = lane / UT;
   const int i = lane % UT;
   const size_t HB = (size_t)a.B * a.U;
   const int C = a.C;
-  const int w0 = task * a.spw;
-  // clusters of the subcarriers of this task that exist
-  const int ntot = min(a.spw, a.W - w0) * C;
+  // clusters of the subcarriers of this task
+  const int ntot = nsub * C;
   const bool user_nu = a.nu != nullptr;
   const float nanv = __int_as_float(0x7fc00000);
 
@@ -157,7 +156,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
     __syncthreads();
 
     // ---- fusion: lane (wlf, u) adds the clusters of its subcarrier, in c order
-    if (wlf < a.spw && i < a.U) {
+    if (wlf < nsub && i < a.U) {
       for (int s = 0; s < nvalid; ++s) {
         const int idx3 = base + s;
         if (idx3 / C != wlf) continue;
@@ -180,7 +179,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
   }
 
   const int w = w0 + wlf;
-  if (wlf < a.spw && w < a.W) {
+  if (wlf < nsub) {
     if (i < a.U) {
       float2 zo;
       float so;
@@ -199,13 +198,29 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int task, Smem<UT> &sm
   }
 }
 
+// Systems per work item: a round of subcarriers (PD) or `spw` subcarriers
+// with all their clusters (FD).
+template <int UT, int PREC, bool FD>
+__host__ __device__ constexpr int task_size(int spw) {
+  return FD ? spw : pd_per<UT, PREC>();
+}
+
+// One wave per workgroup.  Workgroup b of G takes the contiguous share
+// [b W / G, (b+1) W / G) of the systems, in work items of up to task_size
+// systems (with G = ceil(W / task_size), one work item each).
 template <int UT, int PREC, bool FD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_target<UT, PREC, FD>(), 8))) void eq_forward_kernel(const FwdArgs a) {
   __shared__ Smem<UT> sm;
-  if constexpr (FD)
-    fd_task<UT, PREC>(a, blockIdx.x, sm);
-  else
-    pd_task<UT, PREC>(a, blockIdx.x, sm);
+  const int per = task_size<UT, PREC, FD>(a.spw);
+  const int lo = (int)((long long)blockIdx.x * a.W / gridDim.x);
+  const int hi = (int)((long long)(blockIdx.x + 1) * a.W / gridDim.x);
+  for (int w = lo; w < hi; w += per) {
+    const int n = min(per, hi - w);
+    if constexpr (FD)
+      fd_task<UT, PREC>(a, w, n, sm);
+    else
+      pd_task<UT, PREC>(a, w, n, sm);
+  }
 }
 
 __global__ void zero_i32_kernel(int32_t *p, int n) {
@@ -220,9 +235,12 @@ hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s) {
 
 template <int UT, int PREC, bool FD>
 static hipError_t launch_one(const FwdArgs &a, hipStream_t s) {
-  const int per = FD ? a.spw : pd_per<UT, PREC>();
-  const int tasks = (a.W + per - 1) / per;
-  hipLaunchKernelGGL((eq_forward_kernel<UT, PREC, FD>), dim3(tasks), dim3(64), 0, s, a);
+  // one work item per workgroup: the hardware dispatcher refills a freed slot
+  // at once (a one-generation grid with equal shares per workgroup measured
+  // slower: its partial rounds add solves)
+  const int per = task_size<UT, PREC, FD>(a.spw);
+  const int grid = (a.W + per - 1) / per;
+  hipLaunchKernelGGL((eq_forward_kernel<UT, PREC, FD>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

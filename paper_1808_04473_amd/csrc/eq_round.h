@@ -9,7 +9,7 @@ namespace dbpeq {
 template <int UT>
 struct Smem {
   static constexpr int NSYS = 64 / UT;
-  float2 A[NSYS][UT][UT + 1];
+  float2 A[NSYS][UT][UT];  // swizzled rows (lds_el)
   float2 M[NSYS][UT];
   float4 F[NSYS][UT];
   int routed[NSYS];
@@ -32,7 +32,7 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int
   float rowsum = 0.f;
 #pragma unroll
   for (int k = 0; k < UT; ++k) {
-    r.f.a[k] = sm.A[sme][i][k];
+    r.f.a[k] = lds_el<UT>(sm.A[sme], i, k);
     bad |= !finite2(r.f.a[k]);
     rowsum += __builtin_amdgcn_sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
   }
@@ -46,7 +46,10 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int
 
 // One refinement step for the systems of a round: every group's z goes to
 // LDS, the residual pass streams the systems' rows again and each group
-// solves A dz = H^H (y - H z) - rho z with its existing factor.
+// solves A dz = H^H (y - H z) - rho z as dz = X^H (X r) with X = L^{-1}
+// (A^{-1} = X^H X): the columns of X are parked in LDS during the pass,
+// t = X r is read back along rows of X and dz = X^H t uses the reloaded
+// columns, so the factor L is dead once the inverse is formed.
 template <int UT, class Rho, class Seg>
 __device__ __forceinline__ void refine_round(LocalSolve<UT> &r, Smem<UT> &sm, int nvalid, int U,
                                              Rho rhof, Seg seg, bool live) {
@@ -54,9 +57,9 @@ __device__ __forceinline__ void refine_round(LocalSolve<UT> &r, Smem<UT> &sm, in
   const int sme = lane / UT, i = lane % UT;
   __syncthreads();
   sm.M[sme][i] = r.z;
-  // park the inverse columns in the (now free) matrix slot while streaming
+  // row u of the slot holds column u of X: lds_el(A, u, k) = X_ku
 #pragma unroll
-  for (int k = 0; k < UT; ++k) sm.A[sme][i][k] = r.f.x[k];
+  for (int k = 0; k < UT; ++k) lds_el<UT>(sm.A[sme], i, k) = r.f.x[k];
   __syncthreads();
   residual_stream<UT>(
       nvalid, U, seg, [&](int s) { return sm.M[s][lane % UT]; },
@@ -67,10 +70,18 @@ __device__ __forceinline__ void refine_round(LocalSolve<UT> &r, Smem<UT> &sm, in
       });
   __syncthreads();
   asm volatile("" ::: "memory");  // reload the parked columns instead of keeping them live
+  // t_j = sum_u X_ju r_u at lane j
+  float tx = 0.f, ty = 0.f;
 #pragma unroll
-  for (int k = 0; k < UT; ++k) r.f.x[k] = sm.A[sme][i][k];
-  const float4 nv = sm.F[sme][i];
-  const float2 dz = solve<UT>(r.f, i, make_float2(nv.x, nv.y));
+  for (int u = 0; u < UT; ++u) {
+    const float2 x = lds_el<UT>(sm.A[sme], u, i);
+    const float4 rv = sm.F[sme][u];
+    tx = fmaf(x.x, rv.x, fmaf(-x.y, rv.y, tx));
+    ty = fmaf(x.x, rv.y, fmaf(x.y, rv.x, ty));
+  }
+#pragma unroll
+  for (int k = 0; k < UT; ++k) r.f.x[k] = lds_el<UT>(sm.A[sme], i, k);
+  const float2 dz = apply_xh<UT>(r.f, make_float2(tx, ty));
   if (live) {
     r.z.x += dz.x;
     r.z.y += dz.y;
