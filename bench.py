@@ -97,6 +97,114 @@ VARIANTS = [("pd", "fp32"), ("pd", "bf16x3"), ("pd", "bf16_refine"), ("pd", "bf1
             ("fd", "fp32"), ("fd", "bf16x3"), ("fd", "bf16_refine"), ("fd", "bf16x3_refine")]
 
 
+def _timed(fn, steps, warmup):
+    """Median / p10 / p90 of per-call HIP-event times (ms) on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return {"call_ms_median": float(np.median(per)), "call_ms_mean": float(np.mean(per)),
+            "call_ms_p10": float(np.percentile(per, 10)), "call_ms_p90": float(np.percentile(per, 90))}
+
+
+def _rel_err(zg, zr):
+    return float(np.max(np.max(np.abs(zg - zr), -1) / np.max(np.abs(zr), -1)))
+
+
+def extra_measurements(Hn, yn, n0, off, H, y, steps):
+    """The other rows of the path, each timed the same way and parity-sampled
+    against the oracle: single-frame latency (W = 1200), the B = 1024 / U = 32
+    workload in every precision form, ragged batches of 4096 systems, and the
+    FD forward + adjoint of the differentiation workload."""
+    import torch
+    import oracle
+    from paper_1808_04473_amd import api, synth
+    dev = H.device
+    out = {}
+    # single frame of the headline workload
+    H1, y1 = H[:W_FRAME].contiguous(), y[:W_FRAME].contiguous()
+    for mode, fn in (("pd", api.eq_pd), ("fd", api.eq_fd)):
+        out[f"latency_w{W_FRAME}_{mode}_fp32"] = _timed(lambda: fn(H1, y1, n0, off), steps, 3)
+
+    # B = 1024 antennas in 16 clusters of 64, U = 32, 4 frames x 1200 (1.3 GB of H)
+    c3 = [synth.config_batch(3, 10.0, frame=f) for f in range(4)]
+    H3n = np.concatenate([b.H for b in c3]); y3n = np.concatenate([b.y for b in c3])
+    n03, off3 = c3[0].n0, c3[0].cluster_off
+    H3, y3 = torch.from_numpy(H3n).to(dev), torch.from_numpy(y3n).to(dev)
+    W3, B3, U3 = H3n.shape
+    bps3 = bytes_per_system(B3, U3)
+    samp = np.arange(0, W3, W3 // 32)
+    ref3 = {"pd": oracle.eq_pd(H3n[samp], y3n[samp], n03, off3), "fd": oracle.eq_fd(H3n[samp], y3n[samp], n03, off3)}
+    for mode in ("pd", "fd"):
+        fn = api.eq_pd if mode == "pd" else api.eq_fd
+        for prec in ("fp32", "bf16x3", "bf16_refine", "bf16x3_refine"):
+            t = _timed(lambda: fn(H3, y3, n03, off3, precision=prec), steps, 3)
+            z, s2, info = fn(H3, y3, n03, off3, precision=prec, return_info=True)
+            routed = ((info & (1 << 30)) != 0)
+            routed = routed.any(dim=-1) if mode == "fd" else routed
+            zr, sr = ref3[mode]
+            sel = torch.from_numpy(samp).to(dev)
+            t.update({"systems_per_s": W3 / (t["call_ms_mean"] * 1e-3),
+                      "alg_GBps": W3 * bps3 / (t["call_ms_mean"] * 1e-3) / 1e9,
+                      "fp64_routed": int(routed.sum().item()),
+                      "parity_max_rel_err_z": _rel_err(z[sel].cpu().numpy(), zr),
+                      "parity_max_sigma2_db": float(np.max(np.abs(10 * np.log10(s2[sel].cpu().numpy() / sr))))})
+            out[f"B1024_U32_{mode}_{prec}"] = t
+    del H3, y3
+
+    # ragged: 4 independent batches of 4096 systems (beyond the Infinity Cache)
+    rbs = [synth.make_ragged(4096, seed=synth.BASE_SEED + 4 + 17 * k) for k in range(4)]
+    pools = [(torch.from_numpy(rb.H_pool).to(dev), torch.from_numpy(rb.y_pool).to(dev)) for rb in rbs]
+    nbytes = sum(int(np.sum(rb.B.astype(np.int64) * rb.U * 8 + rb.B * 8 + rb.U * 12)) for rb in rbs)
+    for fd in (False, True):
+        plans = [api.Plan.from_ragged(rb, fd=fd) for rb in rbs]
+
+        def run_all():
+            for pl, (hp, yp) in zip(plans, pools):
+                pl.execute(hp, yp)
+        t = _timed(run_all, steps, 2)
+        t.update({"systems_per_s": 4 * 4096 / (t["call_ms_mean"] * 1e-3),
+                  "alg_GBps": nbytes / (t["call_ms_mean"] * 1e-3) / 1e9,
+                  "plan_shape": plans[0].describe()})
+        rb, (hp, yp) = rbs[0], pools[0]
+        z, s2, info = plans[0].execute(hp, yp)
+        zh = z.cpu().numpy()
+        errs = []
+        for k in range(0, rb.nsys, 97):
+            Bk, Uk = int(rb.B[k]), int(rb.U[k])
+            Hk = rb.H_pool[rb.h_off[k]:rb.h_off[k] + Bk * Uk].reshape(1, Bk, Uk)
+            yk = rb.y_pool[rb.y_off[k]:rb.y_off[k] + Bk].reshape(1, Bk)
+            offk = np.concatenate([[0], np.cumsum(rb.cluster_sizes[rb.clus_first[k]:rb.clus_first[k] + rb.C[k]])])
+            zr, _ = (oracle.eq_fd if fd else oracle.eq_pd)(Hk, yk, float(rb.n0[k]), offk)
+            errs.append(_rel_err(zh[rb.z_off[k]:rb.z_off[k] + Uk][None], zr))
+        t["parity_max_rel_err_z"] = float(max(errs))
+        out[f"ragged_4x4096_{'fd' if fd else 'pd'}_fp32"] = t
+        for pl in plans:
+            pl.close()
+    del pools
+
+    # differentiation workload: FD forward + adjoint (w.r.t. H, y, N0), 38,400 systems
+    gz = torch.randn(H.shape[0], U, dtype=torch.complex64, device=dev)
+
+    def fwd_bwd():
+        api.eq_fd(H, y, n0, off)
+        api.eq_fd_backward(H, y, n0, off, gz=gz)
+    t = _timed(fwd_bwd, max(5, steps // 5), 2)
+    W = H.shape[0]
+    # forward reads H, y; adjoint reads H, y and writes grad_H, grad_y
+    t.update({"systems_per_s": W / (t["call_ms_mean"] * 1e-3),
+              "alg_GBps": W * (3 * B * U * 8 + 3 * B * 8) / (t["call_ms_mean"] * 1e-3) / 1e9})
+    out["fd_forward_adjoint_fp32"] = t
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +216,8 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=CPU_SAMPLE_DEFAULT)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (B=1024/U=32, ragged, adjoint, latency)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -232,6 +342,8 @@ def main(argv=None):
                 "hbm_frac": a["hbm_frac"],
                 "parity_max_rel_err_z": a.get("parity_max_rel_err_z"),
                 "fp32_parity_max_rel_err_z": b.get("parity_max_rel_err_z")}
+    if not args.no_extras:
+        out["other_workloads"] = extra_measurements(Hn, yn, n0, off, H, y, min(args.steps, 20))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Hn, yn, n0, off, min(args.cpu_sample, W))
     print(json.dumps(out), flush=True)

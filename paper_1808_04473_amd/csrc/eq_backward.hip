@@ -98,7 +98,6 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
 
   // ---- stream the rows again: grad_H and grad_y
   if (nvalid > 0) {
-    constexpr int RPS = 64 / UT;
     const int g = lane / UT;
     float2 zc = sm.r.M[0][col], lc = sm.L[0][col];
     float2 qc[UT];
@@ -111,14 +110,14 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
         [&](const Slot &b) {
           float2 *gHw = a.gH ? a.gH + (b.Hw - a.H) : nullptr;
           float2 *gyw = a.gy ? a.gy + (b.yw - a.y) : nullptr;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
+          sfor<8>([&](auto E) {
+            constexpr int e = E;
             const float2 h = slot_h<UT>(b, e, U);
             const float hzx = gsum<UT>(h.x * zc.x - h.y * zc.y);
             const float hzy = gsum<UT>(h.x * zc.y + h.y * zc.x);
             const float hlx = gsum<UT>(h.x * lc.x - h.y * lc.y);
             const float hly = gsum<UT>(h.x * lc.y + h.y * lc.x);
-            const float2 yv = slot_y<UT>(b, e);
+            const float2 yv = slot_y<UT, e>(b);
             const float rx = yv.x - hzx, ry = yv.y - hzy;
             // (y - Hz)_row conj(lambda_col) - (H lambda)_row conj(z_col)
             float gx = rx * lc.x + ry * lc.y - (hlx * zc.x + hly * zc.y);
@@ -134,12 +133,12 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
               gx -= 2.f * a.n0 * qx;
               gy -= 2.f * a.n0 * qy;
             }
-            const int row = b.rb + e * RPS + g;
+            const int row = b.rb + slot_row(e, g);
             if (row < b.r1) {
               if (gHw && col < U) gHw[(size_t)row * U + col] = make_float2(gx, gy);
               if (gyw && col == 0) gyw[row] = make_float2(hlx, hly);
             }
-          }
+          });
         },
         [&](int s) {
           if (s + 1 < nvalid) {

@@ -255,37 +255,44 @@ __device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off
   return make_float2(v.x, v.y);
 }
 
+// Row of load step e of group g (lane / UT) within a row block: each group
+// holds 8 consecutive rows, so that y of those rows sits in the group's own
+// DPP row (lanes 0..7 of it) and reaches the other lanes by row broadcast.
+__device__ __forceinline__ int slot_row(int e, int g) { return 8 * g + e; }
+
 // Per-lane byte offsets of the streaming layout (constant over a stream).
 template <int UT>
 struct LaneOff {
-  unsigned h;  // (g * U + col) * 8, or out of range for padded columns
-  unsigned y;  // lane * 8 for the lanes that load y, else out of range
+  unsigned h;  // (8 g U + col) * 8, or out of range for padded columns
+  unsigned y;  // (8 g + c) * 8 for lanes c = lane % 16 < 8, else out of range
   int g;       // row group lane / UT
 };
 
 template <int UT>
 __device__ __forceinline__ LaneOff<UT> lane_offsets(int U) {
-  constexpr int RPB = 8 * (64 / UT);
   const int lane = lane_id();
-  const int col = lane % UT, g = lane / UT;
+  const int col = lane % UT, g = lane / UT, c = lane % 16;
   LaneOff<UT> o;
-  o.h = col < U ? (unsigned)((g * U + col) * 8) : kOutOfRange;
-  o.y = lane < RPB ? (unsigned)(lane * 8) : kOutOfRange;
+  o.h = col < U ? (unsigned)((slot_row(0, g) * U + col) * 8) : kOutOfRange;
+  o.y = c < 8 ? (unsigned)(slot_row(c, g) * 8) : kOutOfRange;
   o.g = g;
   return o;
 }
 
+// Loads the row block at rb of rows [r0, r1).  live = false gives the
+// descriptors zero length: every load is then out of range and returns zero
+// without a memory access (the same instructions, no traffic).
 template <int UT, int AUX>
 __device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const float2 *__restrict__ Hw,
                                           const float2 *__restrict__ yw, int U, int rb, int r0,
-                                          int r1) {
-  constexpr int RPS = 64 / UT;
+                                          int r1, bool live) {
+  const int nrow = live ? r1 - r0 : 0;
   const __amdgpu_buffer_rsrc_t rh =
-      __builtin_amdgcn_make_buffer_rsrc((void *)(Hw + (size_t)r0 * U), (short)0, (r1 - r0) * U * 8, kBufFlags);
+      __builtin_amdgcn_make_buffer_rsrc((void *)(Hw + (size_t)r0 * U), (short)0, nrow * U * 8, kBufFlags);
   const __amdgpu_buffer_rsrc_t ry =
-      __builtin_amdgcn_make_buffer_rsrc((void *)(yw + r0), (short)0, (r1 - r0) * 8, kBufFlags);
+      __builtin_amdgcn_make_buffer_rsrc((void *)(yw + r0), (short)0, nrow * 8, kBufFlags);
   const unsigned rowb = (unsigned)((rb - r0) * U * 8);
-  const unsigned step = (unsigned)(RPS * U * 8);
+  const unsigned step = (unsigned)(U * 8);
 #pragma unroll
   for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2<AUX>(rh, lo.h + rowb + e * step);
   b.yl = buf_ld2<AUX>(ry, lo.y + (unsigned)((rb - r0) * 8));
@@ -296,18 +303,17 @@ __device__ __forceinline__ void load_slot(Slot &b, const LaneOff<UT> &lo, const 
   b.r1 = r1;
 }
 
-// H[rb + e*RPS + g][col] of this lane (zero outside the system).
+// H[rb + slot_row(e, g)][col] of this lane (zero outside the system).
 template <int UT>
 __device__ __forceinline__ float2 slot_h(const Slot &b, int e, int) {
   return b.h[e];
 }
 
-// y[rb + e*RPS + g] of this lane's row in load step e (zero past the end).
-template <int UT>
-__device__ __forceinline__ float2 slot_y(const Slot &b, int e) {
-  constexpr int RPS = 64 / UT;
-  const int src = e * RPS + b.g;
-  return make_float2(__shfl(b.yl.x, src), __shfl(b.yl.y, src));
+// y[rb + slot_row(E, g)] of this lane's row in load step E (zero past the
+// end): lane E of the DPP row holds it.
+template <int UT, int E>
+__device__ __forceinline__ float2 slot_y(const Slot &b) {
+  return make_float2(dpp<DPP_ROW_NEWBCAST + E>(b.yl.x), dpp<DPP_ROW_NEWBCAST + E>(b.yl.y));
 }
 
 // Streams the row blocks of a sequence of systems produced by gen (a
@@ -323,12 +329,13 @@ __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done
   int crb = cur.r0;
   bool more = true;
   const LaneOff<UT> lo = lane_offsets<UT>(U);
-  // Every issue executes the same loads: an exhausted stream re-loads its
-  // last block (a cache hit) so that the number of loads in flight is the
-  // same on every path and the compiler can wait for one block at a time.
+  // Every issue executes the same loads: an exhausted stream issues them
+  // against empty descriptors (no memory access) so that the number of loads
+  // in flight is the same on every path and the compiler can wait for one
+  // block at a time.
   auto issue = [&](Slot &sl) -> bool {
     const bool valid = more;
-    load_slot<UT, AUX>(sl, lo, cur.Hw, cur.yw, U, crb, cur.r0, cur.r1);
+    load_slot<UT, AUX>(sl, lo, cur.Hw, cur.yw, U, crb, cur.r0, cur.r1, valid);
     sl.s = cur.s;
     sl.tk = cur.tk;
     sl.last = crb + RPB >= cur.r1;
@@ -480,15 +487,15 @@ __device__ __forceinline__ void gram_blk(const Slot &sl, int U, Acc<UT> &acc, fl
     acc.ii = mma16(il, ih, acc.ii);
     acc.ii = mma16(ih, ih, acc.ii);
   }
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float2 yv = slot_y<UT>(sl, e);
-    // conj(h) * y, accumulated as a chain of FMAs
-    mfx = fmaf(b.h[e].x, yv.x, mfx);
-    mfx = fmaf(b.h[e].y, yv.y, mfx);
-    mfy = fmaf(b.h[e].x, yv.y, mfy);
-    mfy = fmaf(-b.h[e].y, yv.x, mfy);
-  }
+  // conj(h) * y as FMACs whose y operand is the DPP row broadcast of the
+  // lane that loaded it
+  sfor<8>([&](auto E) {
+    constexpr int e = E;
+    fmac_rowbcast<e, false, e == 0 ? 4 : 0>(mfx, sl.yl.x, b.h[e].x);
+    fmac_rowbcast<e, false, 0>(mfy, sl.yl.y, b.h[e].x);
+    fmac_rowbcast<e, false, 0>(mfx, sl.yl.y, b.h[e].y);
+    fmac_rowbcast<e, true, 0>(mfy, sl.yl.x, b.h[e].y);
+  });
 }
 
 // Gram + matched filter of systems 0..ns-1; done(s, acc, mf) receives each
@@ -519,20 +526,20 @@ __device__ __forceinline__ void residual_stream(int ns, int U, Seg seg, Zc zcf, 
   stream_blocks<UT, kLoadLast>(
       ns, U, seg,
       [&](const Slot &b) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        sfor<8>([&](auto E) {
+          constexpr int e = E;
           const float2 h = slot_h<UT>(b, e, U);
           // (H z)_row = sum over the UT lanes of this row of h * z
           const float px = gsum<UT>(h.x * zc.x - h.y * zc.y);
           const float py = gsum<UT>(h.x * zc.y + h.y * zc.x);
-          const float2 yv = slot_y<UT>(b, e);
+          const float2 yv = slot_y<UT, e>(b);
           const float rx = yv.x - px;
           const float ry = yv.y - py;
           nx = fmaf(h.x, rx, nx);
           nx = fmaf(h.y, ry, nx);
           ny = fmaf(h.x, ry, ny);
           ny = fmaf(-h.y, rx, ny);
-        }
+        });
       },
       [&](int s) {
         done(s, make_float2(colsum<UT>(nx), colsum<UT>(ny)));
