@@ -91,8 +91,10 @@ typedef struct {
 } eq_problem;
 
 /* Bytes of device workspace the forward calls need for this problem (the
-   list of systems routed to the FP64 re-solve).  The caller allocates it;
-   the library never allocates device memory in eq_pd / eq_fd. */
+   queue of systems routed to the FP64 re-solve).  The caller allocates it
+   and fills it with zeros once, before its first use; every call leaves it
+   zero-filled again, so calls that share a workspace must be ordered on one
+   stream.  The library never allocates device memory in eq_pd / eq_fd. */
 size_t eq_workspace_size(const eq_problem *p);
 
 /* Partially decentralised L-MMSE (Section II-C; Section III-A).

@@ -123,7 +123,25 @@ def _check_inputs(H, y):
 def workspace(prob: EqProblem, device) -> torch.Tensor:
     lib = load_library()
     n = lib.eq_workspace_size(ctypes.byref(prob))
-    return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+    # zero-filled once; every call leaves it zero-filled
+    return torch.zeros(max(int(n), 256), dtype=torch.uint8, device=device)
+
+
+# Forward workspaces kept per (device, stream): each call leaves its workspace
+# zero-filled and calls on one stream are ordered, so one zero-fill serves
+# every later call on that stream.
+_WS_CACHE: dict = {}
+
+
+def _cached_workspace(prob: EqProblem, device) -> torch.Tensor:
+    lib = load_library()
+    need = max(int(lib.eq_workspace_size(ctypes.byref(prob))), 256)
+    key = (device.index if device.index is not None else torch.cuda.current_device(), _stream())
+    ws = _WS_CACHE.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.zeros(need, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = ws
+    return ws
 
 
 def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
@@ -141,7 +159,7 @@ def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, ou
         info = torch.empty((W,), dtype=torch.int32, device=H.device)
     else:
         z, s2, info = out
-    ws = workspace(prob, H.device) if ws is None else ws
+    ws = _cached_workspace(prob, H.device) if ws is None else ws
     st = lib.eq_pd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_pd", st)
@@ -166,7 +184,7 @@ def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=
         info = torch.empty((W, C), dtype=torch.int32, device=H.device)
     else:
         z, s2, info = out
-    ws = workspace(prob, H.device) if ws is None else ws
+    ws = _cached_workspace(prob, H.device) if ws is None else ws
     st = lib.eq_fd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(nu), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_fd", st)

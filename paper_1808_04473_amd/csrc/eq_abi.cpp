@@ -66,10 +66,11 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   a.z = reinterpret_cast<float2 *>(z);
   a.s2 = s2;
   a.info = info;
+  // the workspace starts zero-filled and the re-solve kernel leaves it so
   a.fb_count = reinterpret_cast<int32_t *>(ws);
+  a.fb_done = a.fb_count + 1;
   a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (launch_zero_i32(a.fb_count, 1, s) != hipSuccess) return EQ_EHIP;
   if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
   if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
   return EQ_OK;

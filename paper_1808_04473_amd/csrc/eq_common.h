@@ -22,8 +22,9 @@ struct FwdArgs {
   float2 *z;
   float *s2;            // may be nullptr
   int32_t *info;        // may be nullptr
-  int32_t *fb_count;    // FP64 re-solve queue (workspace)
-  int32_t *fb_list;
+  int32_t *fb_count;    // FP64 re-solve queue (workspace): length,
+  int32_t *fb_done;     // blocks of the re-solve kernel that finished,
+  int32_t *fb_list;     // queued systems
   int32_t W, B, U, C;
   float n0, rho, es;
   int32_t spw;          // FD: subcarriers per wave

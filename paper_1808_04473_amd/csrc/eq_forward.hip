@@ -26,7 +26,7 @@ namespace dbpeq {
 // Queue subcarrier w for the FP64 re-solve (one lane calls this).
 __device__ __forceinline__ void enqueue_fp64(const FwdArgs &a, int w) {
   const int pos = atomicAdd(a.fb_count, 1);
-  a.fb_list[pos] = w;
+  if (pos >= 0 && pos < a.W) a.fb_list[pos] = w;  // capacity W
 }
 
 template <int UT, int PREC>

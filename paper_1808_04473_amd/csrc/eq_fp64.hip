@@ -159,14 +159,22 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
   __syncthreads();
 }
 
+// The queue (a.fb_count, a.fb_list) is filled by the forward kernel.  Blocks
+// 0 .. min(n, grid) - 1 take entries; the last of them to finish sets the
+// count and its own completion counter back to zero (every block that takes
+// entries has read the count by then; the others find nothing to do whether
+// they read it before or after), so every call leaves the workspace as the
+// next one expects it, and a call that routed nothing does no atomics.
 template <bool FD>
 __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
   __shared__ F64Smem sm;
-  const int n = *a.fb_count;
+  const int n = min(*a.fb_count, a.W);
+  if ((int)blockIdx.x >= n) return;
   const double rho = (double)a.n0 / (double)a.es;
   const size_t HB = (size_t)a.B * a.U;
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int w = a.fb_list[q];
+    if (w < 0 || w >= a.W) continue;
     auto off = [&](int c) { return FD ? (int)a.off[c] : (c == 0 ? 0 : a.B); };
     auto info = [&](int c, int fail) {
       if (!a.info) return;
@@ -177,14 +185,23 @@ __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
                 (double)a.n0, rho, FD, a.nu ? a.nu + (size_t)w * a.C * a.U : nullptr,
                 a.z + (size_t)w * a.U, a.s2 ? a.s2 + (size_t)w * a.U : nullptr, info);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // every block read the count before it arrives here
+    if (atomicAdd(a.fb_done, 1) == min(n, (int)gridDim.x) - 1) {
+      *a.fb_count = 0;
+      *a.fb_done = 0;
+    }
+  }
 }
 
 template <bool FD>
 __global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) {
   __shared__ F64Smem sm;
-  const int n = *a.fb_count;
+  const int n = min(*a.fb_count, a.nsys);
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int k = a.fb_list[q];
+    if (k < 0 || k >= a.nsys) continue;
     const RSys d = a.sys[k];
     auto off = [&](int c) { return FD ? a.offs[d.off_first + c] : (c == 0 ? 0 : d.B); };
     int worst = 0;

@@ -52,7 +52,7 @@ __device__ __forceinline__ void ragged_pd(const RaggedArgs &a, const RTask &task
       if (a.info) a.info[k] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) {
         const int pos = atomicAdd(a.fb_count, 1);
-        a.fb_list[pos] = k;
+        if (pos >= 0 && pos < a.nsys) a.fb_list[pos] = k;
       }
     }
   }
@@ -134,7 +134,7 @@ __device__ __forceinline__ void ragged_fd(const RaggedArgs &a, const RTask &task
     if (a.info) a.info[k] = code | (routed ? EQ_INFO_FP64 : 0);
     if (routed) {
       const int pos = atomicAdd(a.fb_count, 1);
-      a.fb_list[pos] = k;
+      if (pos >= 0 && pos < a.nsys) a.fb_list[pos] = k;
     }
   }
 }

@@ -180,6 +180,42 @@ def test_ill_conditioned_clusters_take_fp64_path(prec):
         assert max_db_err(s2, sr) <= TOL_DB
 
 
+def _ill_conditioned_batch():
+    rng = np.random.default_rng(9)
+    W, B, U, C = 24, 64, 4, 2
+    b = synth.make_batch(W, B, U, C, 10.0, "qpsk", seed=11)
+    H = b.H.astype(np.complex128).copy()
+    bad = [1, 7, 8, 20]
+    for w in bad:
+        H[w, :, 1] = H[w, :, 0] + 1e-4 * (rng.standard_normal(B) + 1j * rng.standard_normal(B))
+    H = H.astype(np.complex64)
+    y = (H.astype(np.complex128) @ b.s.astype(np.complex128)[..., None])[..., 0].astype(np.complex64)
+    return synth.Batch(H, y, b.s, 1e-9, b.cluster_off), bad, b
+
+
+def test_workspace_left_zeroed_between_calls():
+    """The FP64 queue in the workspace is reset by the call that used it:
+    reusing one workspace for an ill-conditioned batch, a regular batch and
+    the ill-conditioned batch again routes exactly the same systems each time
+    and leaves the queue header at zero."""
+    from paper_1808_04473_amd import api
+    bad_b, bad, good_b = _ill_conditioned_batch()
+    for mode in ("pd", "fd"):
+        fn = api.eq_pd if mode == "pd" else api.eq_fd
+        W, B, U = bad_b.H.shape
+        prob, _k = api.make_problem(W, B, U, bad_b.cluster_off, 1e-9)
+        ws = api.workspace(prob, torch.device("cuda"))
+        for bb, expect in ((bad_b, set(bad)), (good_b, set()), (bad_b, set(bad))):
+            z, s2, info = fn(dev(bb.H), dev(bb.y), bb.n0, bb.cluster_off, return_info=True, ws=ws)
+            torch.cuda.synchronize()
+            flags = (host(info) & (1 << 30)) != 0
+            routed = flags if mode == "pd" else flags.any(axis=1)
+            assert set(np.nonzero(routed)[0]) == expect, (mode, np.nonzero(routed)[0])
+            zr, _ = ref(mode, bb)
+            assert max_rel_err(host(z), zr) <= TOL_Z["fp32"]
+            assert int(ws[:8].view(torch.int32).abs().sum().item()) == 0
+
+
 def test_zero_systems():
     from paper_1808_04473_amd import api
     H = torch.zeros((0, 8, 2), dtype=torch.complex64, device="cuda")
