@@ -302,6 +302,15 @@ def main(argv=None):
               f"{r['alg_GBps']:.0f} GB/s ({100 * r['hbm_frac']:.1f}% of HBM peak)", file=sys.stderr, flush=True)
         del z, s2, info, ws
 
+    # practical read ceiling of this device: one nontemporal read of the same H
+    ceiling = None
+    if not args.no_extras:
+        nb = api.probe_read(H)
+        t = _timed(lambda: api.probe_read(H), min(args.steps, 20), 3)
+        ceiling = nb / (t["call_ms_mean"] * 1e-3) / 1e9
+        for r in results.values():
+            r["frac_of_read_ceiling"] = r["alg_GBps"] / ceiling
+
     head_key = "pd_fp32" if "pd_fp32" in results else next(iter(results))
     head = results[head_key]
     launch_bytes = W * bps
@@ -329,7 +338,9 @@ def main(argv=None):
                      "kernel": "eq_forward_kernel<16, FP32, PD> (+ queue reset and FP64 re-solve "
                                "launches, included in the timed call)",
                      "alg_bytes_per_launch": launch_bytes,
-                     "alg_bytes_per_system": bps},
+                     "alg_bytes_per_system": bps,
+                     "read_ceiling_GBps": ceiling,
+                     "frac_of_read_ceiling": None if ceiling is None else head["alg_GBps"] / ceiling},
         "variants": results,
         "input_generation_s": gen_s,
     }
@@ -339,7 +350,7 @@ def main(argv=None):
         if a and b:
             out.setdefault("bf16_mfma_vs_fp32", {})[mode] = {
                 "form": f"{mode}_bf16x3", "speedup": a["subcarriers_per_s"] / b["subcarriers_per_s"],
-                "hbm_frac": a["hbm_frac"],
+                "hbm_frac": a["hbm_frac"], "frac_of_read_ceiling": a.get("frac_of_read_ceiling"),
                 "parity_max_rel_err_z": a.get("parity_max_rel_err_z"),
                 "fp32_parity_max_rel_err_z": b.get("parity_max_rel_err_z")}
     if not args.no_extras:

@@ -66,6 +66,7 @@ SIGNATURES = [
                                   c_void_p]),
     ("eq_plan_describe", c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     ("eq_plan_destroy", c_int32, [c_void_p]),
+    ("eq_probe_read", c_int32, [c_void_p, c_size_t, c_void_p, c_void_p]),
 ]
 
 
@@ -311,3 +312,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def probe_read(t, sink=None):
+    """Reads every byte of device tensor t once (eq_probe_read); time it on
+    the current stream to obtain the practical HBM read ceiling."""
+    lib = load_library()
+    if t.device.type != "cuda" or not t.is_contiguous():
+        raise ValueError("probe_read takes a contiguous device tensor")
+    nbytes = t.numel() * t.element_size() // 16 * 16
+    if sink is None:
+        sink = torch.empty(1, dtype=torch.float32, device=t.device)
+    _check("eq_probe_read", lib.eq_probe_read(_ptr(t), nbytes, _ptr(sink), _stream()))
+    return nbytes

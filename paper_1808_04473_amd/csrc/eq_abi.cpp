@@ -150,6 +150,13 @@ eq_status eq_fd_backward(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, 
 
 int32_t eq_abi_version(void) { return EQ_ABI_VERSION; }
 
+eq_status eq_probe_read(const void *buf, size_t bytes, float *sink, void *stream) {
+  if (bytes == 0) return EQ_OK;
+  if (!buf || !sink || !aligned(buf, 16) || !aligned(sink, 4) || bytes % 16 != 0) return EQ_EINVAL;
+  if (launch_probe_read(buf, bytes, sink, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return EQ_EHIP;
+  return EQ_OK;
+}
+
 const char *eq_status_string(eq_status s) {
   switch (s) {
     case EQ_OK: return "ok";

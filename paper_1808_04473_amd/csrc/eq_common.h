@@ -53,6 +53,7 @@ struct BwdArgs {
 hipError_t launch_forward(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 hipError_t launch_fp64_resolve(const FwdArgs &a, bool fd, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
+hipError_t launch_probe_read(const void *buf, size_t bytes, float *sink, hipStream_t s);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);

@@ -114,6 +114,15 @@ def test_zero_systems_is_a_noop(lib):
     assert lib.eq_fd(ctypes.byref(prob), None, None, None, None, None, None, None, 0, None) == 0
 
 
+def test_probe_read_validation(lib):
+    # all of these are rejected (or are no-ops) before any HIP call
+    assert lib.eq_probe_read(A, 0, A, None) == 0
+    assert lib.eq_probe_read(None, 1024, A, None) == EINVAL
+    assert lib.eq_probe_read(A, 1024, None, None) == EINVAL
+    assert lib.eq_probe_read(A + 8, 1024, A, None) == EINVAL
+    assert lib.eq_probe_read(A, 1000, A, None) == EINVAL
+
+
 def test_python_binding_refuses_cpu_tensors(lib):
     import torch
     H = torch.zeros((2, 4, 2), dtype=torch.complex64)

@@ -222,3 +222,10 @@ def test_zero_systems():
     y = torch.zeros((0, 8), dtype=torch.complex64, device="cuda")
     z, s2 = api.eq_pd(H, y, 0.1, [0, 8])
     assert z.shape == (0, 2)
+
+
+def test_read_probe_runs():
+    from paper_1808_04473_amd import api
+    t = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
+    assert api.probe_read(t) == 4 << 20
+    torch.cuda.synchronize()
