@@ -123,15 +123,21 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
             float gx = rx * lc.x + ry * lc.y - (hlx * zc.x + hly * zc.y);
             float gy = ry * lc.x - rx * lc.y - (hly * zc.x - hlx * zc.y);
             if (use_q) {
-              float qx = 0.f, qy = 0.f;
+              // (H Q)_{row,col} = sum_k H[row][k] Q[k][col]: H[row][k] is the DPP
+              // row broadcast of lane k, fused into the FMACs; two partial sums
+              // per component for independent chains
+              const BSrc bx = bsrc<UT>(h.x), by = bsrc<UT>(h.y);
+              float q[4] = {0.f, 0.f, 0.f, 0.f};
               sfor<UT>([&](auto K) {
                 constexpr int k = K;
-                const float2 hk = gbcast2<UT, k>(h);
-                qx += hk.x * qc[k].x - hk.y * qc[k].y;
-                qy += hk.x * qc[k].y + hk.y * qc[k].x;
+                constexpr int p = 2 * (k & 1);
+                fmac_rowbcast<k % 16, false, k == 0 ? 4 : 0>(q[p], bpick<k>(bx), qc[k].x);
+                fmac_rowbcast<k % 16, false, 0>(q[p + 1], bpick<k>(bx), qc[k].y);
+                fmac_rowbcast<k % 16, true, k == 0 ? 4 : 0>(q[p], bpick<k>(by), qc[k].y);
+                fmac_rowbcast<k % 16, false, 0>(q[p + 1], bpick<k>(by), qc[k].x);
               });
-              gx -= 2.f * a.n0 * qx;
-              gy -= 2.f * a.n0 * qy;
+              gx -= 2.f * a.n0 * (q[0] + q[2]);
+              gy -= 2.f * a.n0 * (q[1] + q[3]);
             }
             const int row = b.rb + slot_row(e, g);
             if (row < b.r1) {
@@ -299,8 +305,9 @@ __device__ __forceinline__ float fd_backward_task(const BwdArgs &a, int task, BS
   return gn0;
 }
 
+// 3 waves per SIMD at UT = 16 (168 VGPRs), 2 at UT = 32.
 template <int UT, bool FD>
-__global__ __launch_bounds__(64) void eq_backward_kernel(const BwdArgs a, float4 *fwd) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(UT == 16 ? 3 : 2, 8))) void eq_backward_kernel(const BwdArgs a, float4 *fwd) {
   __shared__ BSmem<UT> sm;
   float g = FD ? fd_backward_task<UT>(a, blockIdx.x, sm, fwd) : pd_backward_task<UT>(a, blockIdx.x, sm);
   // wave sum of the grad_N0 shares

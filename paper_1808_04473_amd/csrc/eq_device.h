@@ -57,9 +57,12 @@ constexpr int DPP_ROW_MIRROR = 0x140;    // lane i <-> 15 - i inside a row of 16
 constexpr int DPP_ROW_HMIRROR = 0x141;   // lane i <-> 7 - i inside half rows
 constexpr int DPP_ROW_NEWBCAST = 0x150;  // + k: lane k of each row to the whole row
 
+// Every control used here reads a valid lane, so the bound_ctrl / old value
+// never matter; this form lets the compiler fold the DPP into the add (or
+// other VOP2 instruction) that consumes it.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // Broadcast source of a value v for groups of UT lanes.  A group of 16 lanes
@@ -121,26 +124,22 @@ __device__ __forceinline__ void fmac_rowbcast(float &acc, float src, float b) {
 
 // Sum over the 16 lanes of a DPP row; every lane receives the sum.
 __device__ __forceinline__ float row16_sum(float v) {
-#ifndef EQ_NO_DPP
   v += dpp<DPP_QUAD_XOR1>(v);
   v += dpp<DPP_QUAD_XOR2>(v);
   v += dpp<DPP_ROW_HMIRROR>(v);
   v += dpp<DPP_ROW_MIRROR>(v);
   return v;
-#else
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
-  return v;
-#endif
 }
 
 // Sum / max / any over an aligned group of UT lanes; all lanes get the result.
 template <int UT>
 __device__ __forceinline__ float gsum(float v) {
   v = row16_sum(v);
-  if constexpr (UT == 32) v += __shfl_xor(v, 16);
+  if constexpr (UT == 32) {
+    // the two row sums of the 32-lane group, each replicated over the group
+    const BSrc r = bsrc<32>(v);
+    v = r.lo + r.hi;
+  }
   return v;
 }
 template <int UT>
@@ -713,17 +712,22 @@ __device__ __forceinline__ float2 fwd_subst(const Factor<UT> &f, int i, float2 b
   return t;
 }
 
-// (X^H t)_u = sum_j conj(X_ju) t_j for lane u.
+// (X^H t)_u = sum_j conj(X_ju) t_j for lane u; t_j is the DPP row broadcast
+// of lane j, fused into the FMACs (t does not change here, so one group).
 template <int UT>
 __device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
-  float rx = 0.f, ry = 0.f;
+  const BSrc bx = bsrc<UT>(t.x), by = bsrc<UT>(t.y);
+  float r[4] = {0.f, 0.f, 0.f, 0.f};
   sfor<UT>([&](auto J) {
     constexpr int j = J;
-    const float2 tj = gbcast2<UT, j>(t);
-    rx += f.x[j].x * tj.x + f.x[j].y * tj.y;
-    ry += f.x[j].x * tj.y - f.x[j].y * tj.x;
+    constexpr int p = 2 * (j & 1);
+    // the first reader of each source carries the wait states
+    fmac_rowbcast<j % 16, false, j == 0 ? 4 : 0>(r[p], bpick<j>(bx), f.x[j].x);
+    fmac_rowbcast<j % 16, false, j == 0 ? 4 : 0>(r[p + 1], bpick<j>(by), f.x[j].x);
+    fmac_rowbcast<j % 16, false, 0>(r[p], bpick<j>(by), f.x[j].y);
+    fmac_rowbcast<j % 16, true, 0>(r[p + 1], bpick<j>(bx), f.x[j].y);
   });
-  return make_float2(rx, ry);
+  return make_float2(r[0] + r[2], r[1] + r[3]);
 }
 
 // Factorises A (rows in f.a) and solves A z = m: returns z_u at lane u,

@@ -139,8 +139,10 @@ __device__ __forceinline__ void ragged_fd(const RaggedArgs &a, const RTask &task
   }
 }
 
+// Holds both the UT = 16 and the UT = 32 paths: 2 waves per SIMD (256 VGPRs)
+// for the one-pass forms; the refining forms need more than 256.
 template <int PREC, bool FD>
-__global__ __launch_bounds__(64) void eq_ragged_kernel(const RaggedArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(refines(PREC) ? 1 : 2, 8))) void eq_ragged_kernel(const RaggedArgs a) {
   __shared__ union {
     Smem<16> s16;
     Smem<32> s32;
