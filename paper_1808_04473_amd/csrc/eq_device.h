@@ -320,8 +320,17 @@ __device__ __forceinline__ float2 slot_y(const Slot &b) {
 // the loads of the next two blocks in flight while body(slot) consumes the
 // current one; done(slot) follows the last block of each system, while the
 // next blocks' loads are still in flight.
+// Ring depth of the row-block stream: two blocks in flight while one is
+// consumed (a fourth slot measured no faster at either group width, and
+// spills in the refining forms).
+template <int UT>
+constexpr int stream_depth() {
+  return 3;
+}
+
 template <int UT, int AUX, class Gen, class Body, class Done>
 __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done) {
+  constexpr int DEPTH = stream_depth<UT>();
   constexpr int RPB = 8 * (64 / UT);
   SysRef cur;
   if (!gen(cur)) return;
@@ -353,78 +362,75 @@ __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done
     }
     return valid;
   };
-#ifndef EQ_STREAM_DEPTH
-#define EQ_STREAM_DEPTH 3
-#endif
   // sched_barrier keeps each block's loads where they are issued: the
   // scheduler must not sink them into (or hoist the consumer above) the
   // previous block's arithmetic.
-#if EQ_STREAM_DEPTH == 4
-  // four-slot ring: three blocks in flight while one is consumed
-  Slot sa, sb, sc, sd;
-  issue(sa);
-  bool vb = issue(sb);
-  bool vc = issue(sc);
-  while (true) {
-    const bool vd = issue(sd);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sa);
-    if (sa.last) done(sa);
-    if (!vb) break;
-    const bool va = issue(sa);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sb);
-    if (sb.last) done(sb);
-    if (!vc) break;
-    vb = issue(sb);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sc);
-    if (sc.last) done(sc);
-    if (!vd) break;
-    vc = issue(sc);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sd);
-    if (sd.last) done(sd);
-    if (!va) break;
+  if constexpr (DEPTH == 4) {
+    // four-slot ring: three blocks in flight while one is consumed
+    Slot sa, sb, sc, sd;
+    issue(sa);
+    bool vb = issue(sb);
+    bool vc = issue(sc);
+    while (true) {
+      const bool vd = issue(sd);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sa);
+      if (sa.last) done(sa);
+      if (!vb) break;
+      const bool va = issue(sa);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sb);
+      if (sb.last) done(sb);
+      if (!vc) break;
+      vb = issue(sb);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sc);
+      if (sc.last) done(sc);
+      if (!vd) break;
+      vc = issue(sc);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sd);
+      if (sd.last) done(sd);
+      if (!va) break;
+    }
+  } else if constexpr (DEPTH == 3) {
+    Slot sa, sb, sc;
+    issue(sa);
+    bool vb = issue(sb);
+    while (true) {
+      const bool vc = issue(sc);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sa);
+      if (sa.last) done(sa);
+      if (!vb) break;
+      const bool va = issue(sa);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sb);
+      if (sb.last) done(sb);
+      if (!vc) break;
+      vb = issue(sb);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sc);
+      if (sc.last) done(sc);
+      if (!va) break;
+    }
+  } else {
+    // two-slot ring: one block in flight while the other is consumed
+    Slot sa, sb;
+    issue(sa);
+    while (true) {
+      const bool vb = issue(sb);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sa);
+      if (sa.last) done(sa);
+      if (!vb) break;
+      const bool va = issue(sa);
+      __builtin_amdgcn_sched_barrier(0);
+      body(sb);
+      if (sb.last) done(sb);
+      if (!va) break;
+    }
   }
-#elif EQ_STREAM_DEPTH == 3
-  Slot sa, sb, sc;
-  issue(sa);
-  bool vb = issue(sb);
-  while (true) {
-    const bool vc = issue(sc);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sa);
-    if (sa.last) done(sa);
-    if (!vb) break;
-    const bool va = issue(sa);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sb);
-    if (sb.last) done(sb);
-    if (!vc) break;
-    vb = issue(sb);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sc);
-    if (sc.last) done(sc);
-    if (!va) break;
-  }
-#else
-  // two-slot ring: one block in flight while the other is consumed
-  Slot sa, sb;
-  issue(sa);
-  while (true) {
-    const bool vb = issue(sb);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sa);
-    if (sa.last) done(sa);
-    if (!vb) break;
-    const bool va = issue(sa);
-    __builtin_amdgcn_sched_barrier(0);
-    body(sb);
-    if (sb.last) done(sb);
-    if (!va) break;
-  }
-#endif
 }
 
 // Fixed list of systems 0..ns-1 described by seg(s, Hw, yw, r0, r1);

@@ -20,6 +20,9 @@
 #ifndef EQ_WAVES_PER_EU
 #define EQ_WAVES_PER_EU 4
 #endif
+#ifndef EQ_PD_PER32
+#define EQ_PD_PER32 1
+#endif
 
 namespace dbpeq {
 
@@ -29,9 +32,13 @@ __device__ __forceinline__ void enqueue_fp64(const FwdArgs &a, int w) {
   if (pos >= 0 && pos < a.W) a.fb_list[pos] = w;  // capacity W
 }
 
+// PD systems per work item.  A 32-lane group streams 32 KiB..1 MiB per
+// system, so one system per item keeps the work items short enough to fill
+// the device several times over (two per item left most of it idle during
+// the last generation of workgroups).
 template <int UT, int PREC>
 constexpr int pd_per() {
-  return refines(PREC) && UT == 16 ? 2 : 64 / UT;
+  return UT == 32 ? EQ_PD_PER32 : (refines(PREC) ? 2 : 64 / UT);
 }
 
 // Occupancy target.  UT = 16: 4 waves per SIMD (128 VGPRs) for the
