@@ -701,6 +701,33 @@ __device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
   });
 }
 
+// The same inverse with L read from LDS instead of registers: Ls holds L
+// (row i written by lane i) with 1 / L_jj on the diagonal, and every lane of
+// a group reads the same element (an LDS broadcast).  The rows of L in
+// registers are dead once they are stored, which is what the 32-lane groups
+// need: there L and L^{-1} together take 128 VGPRs.
+template <int UT>
+__device__ __forceinline__ void inverse_columns_lds(Factor<UT> &f, int u, float2 (*Ls)[UT]) {
+  u = opaque_idx(u);
+#pragma unroll
+  for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+  sfor<UT>([&](auto J) {
+    constexpr int j = J;
+    const float invj = lds_el<UT>(Ls, j, j).x;
+    f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
+    // x_i -= L_ij x_j
+    sfor<UT>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (i > j) {
+        const float2 l = lds_el<UT>(Ls, i, j);
+        f.x[i].x = fmaf(-l.x, f.x[j].x, fmaf(l.y, f.x[j].y, f.x[i].x));
+        f.x[i].y = fmaf(-l.x, f.x[j].y, fmaf(-l.y, f.x[j].x, f.x[i].y));
+      }
+    });
+    step_fence();
+  });
+}
+
 // t = L^{-1} b by forward substitution; lane i holds b_i on entry, t_i on exit.
 template <int UT>
 __device__ __forceinline__ float2 fwd_subst(const Factor<UT> &f, int i, float2 b) {
@@ -740,12 +767,24 @@ __device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
 // fills f.x (columns of L^{-1}) and sets `fail` (0 or first bad pivot + 1).
 // The forward substitution runs before the inverse so the two independent
 // chains are not interleaved by the compiler.
+//
+// Ls (optional) is the LDS matrix slot the system was loaded from: with it,
+// 32-lane groups store L there and form the inverse from LDS.
 template <int UT>
-__device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail) {
+__device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail,
+                                               float2 (*Ls)[UT] = nullptr) {
   fail = cholesky<UT>(f, i);
   const float2 t = fwd_subst<UT>(f, i, m);
   asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));
-  inverse_columns<UT>(f, i);
+  if (UT == 32 && Ls) {
+    // row i of L, with 1 / L_ii on the diagonal
+#pragma unroll
+    for (int k = 0; k < UT; ++k) lds_el<UT>(Ls, i, k) = k == i ? make_float2(f.dinv, 0.f) : f.a[k];
+    __syncthreads();
+    inverse_columns_lds<UT>(f, i, Ls);
+  } else {
+    inverse_columns<UT>(f, i);
+  }
   return apply_xh<UT>(f, t);
 }
 

@@ -52,9 +52,8 @@ constexpr int waves_target() {
   return (refines(PREC) || (FD && PREC == PREC_BF16X3_NR)) ? 3 : EQ_WAVES_PER_EU;
 }
 
-template <int UT, int PREC>
-__device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, Smem<UT> &sm) {
-  constexpr int NSYS = 64 / UT;
+template <int UT, int PREC, class SM>
+__device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, SM &sm) {
   const int lane = lane_id();
   const int sme = lane / UT;
   const int i = lane % UT;
@@ -73,7 +72,7 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, Sm
     store_gram<UT>(sm.A[s], acc, a.rho);
     if (lane < UT) sm.M[s][lane] = mf;
   });
-  for (int s = nvalid; s < NSYS; ++s) {
+  for (int s = nvalid; s < SM::NS; ++s) {
     store_identity<UT>(sm.A[s]);
     if (lane < UT) sm.M[s][lane] = make_float2(0.f, 0.f);
   }
@@ -83,7 +82,7 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, Sm
   const int w = w0 + sme;
   const bool live = sme < nvalid;
   LocalSolve<UT> r;
-  local_solve<UT>(r, sm, sme, i, a.U);
+  local_solve<UT>(r, sm, slot_of<SM>(sme), i, a.U);
   if constexpr (refines(PREC)) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
   const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
@@ -101,8 +100,8 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, Sm
   }
 }
 
-template <int UT, int PREC>
-__device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, Smem<UT> &sm) {
+template <int UT, int PREC, class SM>
+__device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, SM &sm) {
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
   const int sme = lane / UT;
@@ -217,7 +216,8 @@ __host__ __device__ constexpr int task_size(int spw) {
 // systems (with G = ceil(W / task_size), one work item each).
 template <int UT, int PREC, bool FD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_target<UT, PREC, FD>(), 8))) void eq_forward_kernel(const FwdArgs a) {
-  __shared__ Smem<UT> sm;
+  // PD work items of fewer systems than lane groups need fewer matrix slots
+  __shared__ Smem<UT, FD ? 64 / UT : (pd_per<UT, PREC>() < 64 / UT ? pd_per<UT, PREC>() : 64 / UT)> sm;
   const int per = task_size<UT, PREC, FD>(a.spw);
   const int lo = (int)((long long)blockIdx.x * a.W / gridDim.x);
   const int hi = (int)((long long)(blockIdx.x + 1) * a.W / gridDim.x);

@@ -6,14 +6,25 @@
 
 namespace dbpeq {
 
-template <int UT>
+// NS matrix slots (one per system of a round by default; fewer when the
+// work items hold fewer systems than there are lane groups, which leaves
+// room for more waves per CU).
+template <int UT, int NSLOT = 64 / UT>
 struct Smem {
   static constexpr int NSYS = 64 / UT;
-  float2 A[NSYS][UT][UT];  // swizzled rows (lds_el)
-  float2 M[NSYS][UT];
-  float4 F[NSYS][UT];
+  static constexpr int NS = NSLOT;
+  float2 A[NS][UT][UT];  // swizzled rows (lds_el)
+  float2 M[NS][UT];
+  float4 F[NS][UT];
   int routed[NSYS];
 };
+
+// LDS slot of lane group g: groups beyond the slots alias the last one (they
+// then solve a copy of that system, and write nothing).
+template <class SM>
+__device__ __forceinline__ int slot_of(int g) {
+  return g < SM::NS ? g : SM::NS - 1;
+}
 
 // Loads row i of system `sme` from LDS and factorises / solves it.
 template <int UT>
@@ -26,8 +37,8 @@ struct LocalSolve {
   bool bad;
 };
 
-template <int UT>
-__device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int sme, int i, int U) {
+template <int UT, class SM>
+__device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, int i, int U) {
   bool bad = false;
   float rowsum = 0.f;
 #pragma unroll
@@ -40,7 +51,9 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int
   bad |= !finite2(m);
   r.bad = gany<UT>(bad);
   r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
-  r.z = factor_solve<UT>(r.f, i, m, r.fail);
+  // with fewer slots than groups (PD items of one 32-lane system) the freed
+  // registers raise occupancy, so the inverse reads L from LDS there
+  r.z = factor_solve<UT>(r.f, i, m, r.fail, SM::NS < SM::NSYS ? sm.A[sme] : nullptr);
   r.d = inv_diag<UT>(r.f);
 }
 
@@ -50,11 +63,11 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, Smem<UT> &sm, int
 // (A^{-1} = X^H X): the columns of X are parked in LDS during the pass,
 // t = X r is read back along rows of X and dz = X^H t uses the reloaded
 // columns, so the factor L is dead once the inverse is formed.
-template <int UT, class Rho, class Seg>
-__device__ __forceinline__ void refine_round(LocalSolve<UT> &r, Smem<UT> &sm, int nvalid, int U,
+template <int UT, class SM, class Rho, class Seg>
+__device__ __forceinline__ void refine_round(LocalSolve<UT> &r, SM &sm, int nvalid, int U,
                                              Rho rhof, Seg seg, bool live) {
   const int lane = lane_id();
-  const int sme = lane / UT, i = lane % UT;
+  const int sme = slot_of<SM>(lane / UT), i = lane % UT;
   __syncthreads();
   sm.M[sme][i] = r.z;
   // row u of the slot holds column u of X: lds_el(A, u, k) = X_ku
