@@ -46,23 +46,27 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
 
   __syncthreads();  // the matrix slots are reused for Q below
   if (use_q) {
-    // column i of A^{-1}: ainv[k] = sum_m conj(X_mk) X_mi (X = L^{-1}, lane k holds column k)
+    // column i of A^{-1} = X^H X: ainv[k] = sum_m conj(X_mk) X_mi (X = L^{-1},
+    // lane k holds column k), one m at a time over all k: X_mk is the DPP
+    // broadcast of lane k fused into the FMACs, and the UT sums are
+    // independent
     float2 ainv[UT];
-    float dep = 0.f;
-    sfor<UT>([&](auto K) {
-      constexpr int k = K;
-      float ax = 0.f, ay = 0.f;
-      sfor<UT>([&](auto M) {
-        constexpr int m = M;
-        float2 src = r.f.x[m];
-        asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
-        const float2 xmk = gbcast2<UT, k>(src);
-        // conj(xmk) * x[m]
-        ax += xmk.x * r.f.x[m].x + xmk.y * r.f.x[m].y;
-        ay += xmk.x * r.f.x[m].y - xmk.y * r.f.x[m].x;
+#pragma unroll
+    for (int k = 0; k < UT; ++k) ainv[k] = make_float2(0.f, 0.f);
+    sfor<UT>([&](auto M) {
+      constexpr int m = M;
+      const BSrc bx = bsrc<UT>(r.f.x[m].x), by = bsrc<UT>(r.f.x[m].y);
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        // conj(X_mk) X_mi
+        fmac_rowbcast<k % 16, false, k == 0 ? 4 : 0>(ainv[k].x, bpick<k>(bx), r.f.x[m].x);
+        fmac_rowbcast<k % 16, false, k == 0 ? 4 : 0>(ainv[k].y, bpick<k>(bx), r.f.x[m].y);
       });
-      ainv[k] = make_float2(ax, ay);
-      dep = ax;
+      sfor<UT>([&](auto K) {
+        constexpr int k = K;
+        fmac_rowbcast<k % 16, false, k == 0 ? 4 : 0>(ainv[k].x, bpick<k>(by), r.f.x[m].y);
+        fmac_rowbcast<k % 16, true, 0>(ainv[k].y, bpick<k>(by), r.f.x[m].x);
+      });
       step_fence();
     });
     // column i of Q: Q_ki = sum_u A^{-1}_ku gs_u A^{-1}_ui, A^{-1}_ku from lane u
@@ -73,20 +77,34 @@ __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm,
 #pragma unroll
     for (int k = 0; k < UT; ++k) tr += ainv[k].x * ainv[k].x + ainv[k].y * ainv[k].y;
     gn0 -= a.n0 * gsc * tr * inv_es;  // tr(Q) = sum_u gs_u sum_k |A^{-1}_ku|^2
-    dep = 0.f;
+    float dep = 0.f;
     sfor<UT>([&](auto Uu) {
       constexpr int u = Uu;
       const float gsu = gbcast<UT, u>(gsc);
       const float2 w = make_float2(ainv[u].x * gsu, ainv[u].y * gsu);  // gs_u A^{-1}_ui
-      sfor<UT>([&](auto K) {
-        constexpr int k = K;
-        float2 src = ainv[k];
-        asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
-        const float2 aku = gbcast2<UT, u>(src);
-        q[k].x += aku.x * w.x - aku.y * w.y;
-        q[k].y += aku.x * w.y + aku.y * w.x;
-      });
-      dep = q[UT - 1].x;
+      // q[k] += A^{-1}_ku w with A^{-1}_ku = ainv[k] of lane u
+      if constexpr (UT == 16) {
+        // ainv[k] itself is the DPP source (not written here)
+        sfor<UT>([&](auto K) {
+          constexpr int k = K;
+          fmac_rowbcast<u, false, u == 0 && k == 0 ? 4 : 0>(q[k].x, ainv[k].x, w.x);
+          fmac_rowbcast<u, false, 0>(q[k].y, ainv[k].x, w.y);
+          fmac_rowbcast<u, true, 0>(q[k].x, ainv[k].y, w.y);
+          fmac_rowbcast<u, false, 0>(q[k].y, ainv[k].y, w.x);
+        });
+      } else {
+        // a swap per source and lane: broadcasts from registers, each step tied
+        // to the previous one so that they are not all hoisted
+        sfor<UT>([&](auto K) {
+          constexpr int k = K;
+          float2 src = ainv[k];
+          asm volatile("" : "+v"(src.x), "+v"(src.y) : "v"(dep));
+          const float2 aku = gbcast2<UT, u>(src);
+          q[k].x += aku.x * w.x - aku.y * w.y;
+          q[k].y += aku.x * w.y + aku.y * w.x;
+        });
+        dep = q[UT - 1].x;
+      }
       step_fence();
     });
 #pragma unroll
