@@ -13,7 +13,8 @@ no blocking, fusion or reordering beyond what the formulas state.
 
 Modules
 -------
-lmmse        forward PD / FD L-MMSE (Sections II-C, III-A, IV-A, IV-B)
+lmmse        forward PD / FD L-MMSE (Sections II-C, III-A, IV-A, IV-B), also with
+             several receive vectors per channel matrix (Section VI-B)
 adjoint      analytic gradients of both equalisers (derived, not in the paper)
 asymptotics  large-system SINR closed forms (Theorem 1, Corollary 1, Lemma 5)
 
@@ -24,13 +25,14 @@ unpinned".
 """
 from .lmmse import (local_statistics, lmmse_estimate, lmmse_error_variance,
                     lmmse_error_variance_simplified, cond_estimate, eq_pd, eq_fd,
-                    optimal_fusion_weights, eq_centralized)
+                    optimal_fusion_weights, eq_centralized, eq_pd_symbols, eq_fd_symbols)
 from .adjoint import pd_backward, fd_backward
 from .asymptotics import (sinr_pd_lmmse, sinr_fd_lmmse, tse_hanly_lmmse_sigma2)
 
 __all__ = [
     "local_statistics", "lmmse_estimate", "lmmse_error_variance",
     "lmmse_error_variance_simplified", "cond_estimate", "eq_pd", "eq_fd",
-    "optimal_fusion_weights", "eq_centralized", "pd_backward", "fd_backward",
+    "optimal_fusion_weights", "eq_centralized", "eq_pd_symbols", "eq_fd_symbols",
+    "pd_backward", "fd_backward",
     "sinr_pd_lmmse", "sinr_fd_lmmse", "tse_hanly_lmmse_sigma2",
 ]

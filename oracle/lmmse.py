@@ -135,3 +135,57 @@ def eq_fd(H, y, n0, cluster_off, nu=None, es=1.0, return_local=False):
     if return_local:
         return z, s2, dict(z_c=z_c, s2_c=s2_c, nu=w, G_c=Gc, m_c=mc)
     return z, s2
+
+
+def eq_pd_symbols(H, Y, n0, cluster_off, es=1.0):
+    """PD L-MMSE of N_sym receive vectors per channel matrix (Section VI-B:
+    the Gram matrices are formed once per subcarrier and reused over the OFDM
+    symbols of the coherence time; the matched filter is formed for every
+    symbol).
+
+    H [W][B][U], Y [W][S][B]; returns Z [W][S][U] and sigma2 [W][U] (the error
+    variance does not depend on the receive vector).
+    """
+    H = _c128(H)
+    Y = _c128(Y)
+    off = [int(v) for v in cluster_off]
+    W, B, U = H.shape
+    G = np.zeros((W, U, U), np.complex128)
+    M = np.zeros((W, U, Y.shape[1]), np.complex128)
+    for c in range(len(off) - 1):
+        Hc = H[:, off[c]:off[c + 1], :]
+        G += _herm(Hc) @ Hc
+        # H_c^H [y_1 ... y_S] restricted to the cluster's rows
+        M += _herm(Hc) @ np.swapaxes(Y[:, :, off[c]:off[c + 1]], 1, 2)
+    A = G + (float(n0) / float(es)) * np.eye(U)
+    Z = np.swapaxes(np.linalg.solve(A, M), 1, 2)
+    s2 = lmmse_error_variance(G, n0, es)
+    return Z, s2
+
+
+def eq_fd_symbols(H, Y, n0, cluster_off, nu=None, es=1.0):
+    """FD L-MMSE of N_sym receive vectors per channel matrix: local estimates
+    z_{c,s} = (G_c + rho I)^{-1} H_c^H y_{c,s} for every symbol, fused with the
+    weights of Lemma 1 (which depend on the local error variances only, so
+    they are the same for every symbol) or the given `nu` [W][C][U].
+    Returns Z [W][S][U] and sigma2 [W][U].
+    """
+    H = _c128(H)
+    Y = _c128(Y)
+    off = [int(v) for v in cluster_off]
+    W, B, U = H.shape
+    S = Y.shape[1]
+    C = len(off) - 1
+    rho = float(n0) / float(es)
+    z_c = np.empty((W, C, S, U), np.complex128)
+    s2_c = np.empty((W, C, U), np.float64)
+    for c in range(C):
+        Hc = H[:, off[c]:off[c + 1], :]
+        Gc = _herm(Hc) @ Hc
+        Mc = _herm(Hc) @ np.swapaxes(Y[:, :, off[c]:off[c + 1]], 1, 2)
+        z_c[:, c] = np.swapaxes(np.linalg.solve(Gc + rho * np.eye(U), Mc), 1, 2)
+        s2_c[:, c] = lmmse_error_variance(Gc, n0, es)
+    w = optimal_fusion_weights(s2_c) if nu is None else np.asarray(nu, np.float64)
+    Z = np.sum(w[:, :, None, :] * z_c, axis=1)
+    s2 = np.sum(w * w * s2_c, axis=1)
+    return Z, s2

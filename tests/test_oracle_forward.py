@@ -275,3 +275,52 @@ def test_empirical_sinr_matches_large_system_limit(snr_db):
     assert emp_fd <= emp_pd
     # for the MMSE estimate (PD) the unbiased SINR is also E_s/MSE - 1
     assert abs(10 * math.log10((1.0 / np.mean(np.abs(zp - s) ** 2) - 1.0) / th_pd)) < 0.4
+
+
+# ---------------------------------------------------------------- several symbols per channel
+def _sym_case(W=5, B=24, U=4, S=3, off=(0, 8, 24), seed=31):
+    rng = np.random.default_rng(seed)
+    H = (rng.standard_normal((W, B, U)) + 1j * rng.standard_normal((W, B, U))) / np.sqrt(2 * B)
+    Y = rng.standard_normal((W, S, B)) + 1j * rng.standard_normal((W, S, B))
+    return H, Y, 0.05, list(off)
+
+
+def test_symbols_reduce_to_one_vector_per_call():
+    """Every symbol of the multi-symbol PD / FD equals the single-vector
+    equaliser applied to that symbol's receive vector."""
+    H, Y, n0, off = _sym_case()
+    Zp, sp = oracle.eq_pd_symbols(H, Y, n0, off)
+    Zf, sf = oracle.eq_fd_symbols(H, Y, n0, off)
+    for s in range(Y.shape[1]):
+        zp, sp1 = oracle.eq_pd(H, Y[:, s], n0, off)
+        zf, sf1 = oracle.eq_fd(H, Y[:, s], n0, off)
+        np.testing.assert_allclose(Zp[:, s], zp, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(Zf[:, s], zf, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(sp, sp1, rtol=1e-13)
+        np.testing.assert_allclose(sf, sf1, rtol=1e-13)
+
+
+def test_symbols_linear_in_the_receive_vectors():
+    """L-MMSE is linear in y: Z(a Y1 + b Y2) = a Z(Y1) + b Z(Y2), for PD and
+    FD (the FD weights do not depend on y)."""
+    H, Y1, n0, off = _sym_case(seed=32)
+    _, Y2, _, _ = _sym_case(seed=33)
+    a, b = 0.7 - 0.2j, -1.3 + 0.4j
+    for fn in (oracle.eq_pd_symbols, oracle.eq_fd_symbols):
+        Z, _ = fn(H, a * Y1 + b * Y2, n0, off)
+        Z1, _ = fn(H, Y1, n0, off)
+        Z2, _ = fn(H, Y2, n0, off)
+        np.testing.assert_allclose(Z, a * Z1 + b * Z2, rtol=1e-11, atol=1e-13)
+
+
+def test_symbols_brute_force_inverse():
+    """Tiny PD case against an explicit inverse and explicit loops."""
+    H, Y, n0, off = _sym_case(W=2, B=6, U=3, S=2, off=(0, 2, 6), seed=34)
+    Z, s2 = oracle.eq_pd_symbols(H, Y, n0, off)
+    for w in range(2):
+        G = H[w].conj().T @ H[w]
+        Ainv = np.linalg.inv(G + n0 * np.eye(3))
+        for s in range(2):
+            m = np.array([sum(np.conj(H[w, b, u]) * Y[w, s, b] for b in range(6)) for u in range(3)])
+            np.testing.assert_allclose(Z[w, s], Ainv @ m, rtol=1e-12)
+        np.testing.assert_allclose(s2[w], n0 * np.real(np.diag(Ainv)), rtol=1e-12)
