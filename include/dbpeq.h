@@ -48,6 +48,7 @@ extern "C" {
 #define EQ_MAX_U 32          /* users per system */
 #define EQ_MAX_B 65535       /* antennas per system */
 #define EQ_MAX_C 1024        /* clusters per system */
+#define EQ_MAX_SYM 1024      /* receive vectors per channel matrix (eq_*_sym) */
 #define EQ_INFO_FP64 (1 << 30)
 #define EQ_COND_LIMIT 1.0e4f
 
@@ -118,6 +119,25 @@ eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
 eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
                 const float *nu, eq_c32 *z, float *sigma2, int32_t *info,
                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Several receive vectors per channel matrix (Section VI-B): the OFDM
+   symbols of one coherence interval share H, so the Gram matrices, their
+   factors and sigma2 are formed once per subcarrier and applied to all nsym
+   receive vectors; only the matched filters are formed per vector.
+   Y [W][nsym][B] (receive vector s of subcarrier w at Y + (w*nsym + s)*B),
+   Z [W][nsym][U] likewise; sigma2 [W][U] and info ([W] for PD, [W][C] for
+   FD) as for eq_pd / eq_fd, which these equal vector by vector (nsym = 1 is
+   the single-vector problem).  nsym in 1..EQ_MAX_SYM; the vectors are
+   processed in tiles of 16 (U <= 16) or 32 (U > 16), and each tile reads H
+   once.  Precision EQ_FP32 or EQ_BF16X3 (the refining forms return
+   EQ_ENOTSUP).  Same workspace as eq_pd / eq_fd. */
+eq_status eq_pd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H,
+                    const eq_c32 *Y, eq_c32 *Z, float *sigma2, int32_t *info,
+                    void *workspace, size_t workspace_bytes, void *stream);
+eq_status eq_fd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H,
+                    const eq_c32 *Y, const float *nu, eq_c32 *Z, float *sigma2,
+                    int32_t *info, void *workspace, size_t workspace_bytes,
+                    void *stream);
 
 /* Bytes of device workspace the backward calls need. */
 size_t eq_backward_workspace_size(const eq_problem *p);

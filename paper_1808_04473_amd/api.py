@@ -55,6 +55,10 @@ SIGNATURES = [
                         c_void_p, c_size_t, c_void_p]),
     ("eq_fd", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                         c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_pd_sym", c_int32, [POINTER(EqProblem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_fd_sym", c_int32, [POINTER(EqProblem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_pd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_fd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -190,6 +194,61 @@ def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_fd", st)
     return (z, s2, info) if return_info else (z, s2)
+
+
+def _check_sym_inputs(H, Y):
+    if not (isinstance(H, torch.Tensor) and isinstance(Y, torch.Tensor)):
+        raise TypeError("H and Y must be torch tensors")
+    if H.device.type != "cuda" or Y.device.type != "cuda":
+        raise ValueError("H and Y must be on a HIP device (no CPU fallback)")
+    if H.dtype != torch.complex64 or Y.dtype != torch.complex64:
+        raise TypeError("H and Y must be complex64")
+    if H.dim() != 3 or Y.dim() != 3 or H.shape[0] != Y.shape[0] or H.shape[1] != Y.shape[2]:
+        raise ValueError(f"shapes H {tuple(H.shape)} / Y {tuple(Y.shape)} are not [W][B][U] / [W][S][B]")
+    return H.contiguous(), Y.contiguous()
+
+
+def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws):
+    lib = load_library()
+    H, Y = _check_sym_inputs(H, Y)
+    W, B, U = H.shape
+    S = Y.shape[1]
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    C = prob.C
+    if nu is not None:
+        if not fd:
+            raise ValueError("nu applies to FD only")
+        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
+            raise ValueError("nu must be float32 [W][C][U] on the same device")
+        nu = nu.contiguous()
+    if out is None:
+        z = torch.empty((W, S, U), dtype=torch.complex64, device=H.device)
+        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+        info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
+    else:
+        z, s2, info = out
+    ws = _cached_workspace(prob, H.device) if ws is None else ws
+    if fd:
+        st = lib.eq_fd_sym(ctypes.byref(prob), S, _ptr(H), _ptr(Y), _ptr(nu), _ptr(z), _ptr(s2),
+                           _ptr(info), _ptr(ws), ws.numel(), _stream())
+    else:
+        st = lib.eq_pd_sym(ctypes.byref(prob), S, _ptr(H), _ptr(Y), _ptr(z), _ptr(s2), _ptr(info),
+                           _ptr(ws), ws.numel(), _stream())
+    _check("eq_fd_sym" if fd else "eq_pd_sym", st)
+    return (z, s2, info) if return_info else (z, s2)
+
+
+def eq_pd_sym(H, Y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
+              ws=None):
+    """PD L-MMSE of S receive vectors per channel matrix: H [W][B][U], Y [W][S][B]
+    -> (Z [W][S][U] c64, sigma2 [W][U] f32).  Precision "fp32" or "bf16x3"."""
+    return _sym_call(False, H, Y, n0, cluster_off, None, precision, es, return_info, out, ws)
+
+
+def eq_fd_sym(H, Y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
+              out=None, ws=None):
+    """FD L-MMSE of S receive vectors per channel matrix (weights as eq_fd)."""
+    return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws)
 
 
 def _bwd_workspace(prob: EqProblem, device) -> torch.Tensor:

@@ -47,6 +47,9 @@ void fill_fwd(FwdArgs &a, const eq_problem *p) {
   a.rho = p->n0 / p->es;
   for (int c = 0; c <= p->C; ++c) a.off[c] = (uint16_t)p->cluster_off[c];
   a.spw = fd_spw(ut_for(p->U), p->C);
+  a.nsym = 1;
+  a.ysw = p->B;
+  a.zsw = p->U;
 }
 
 eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
@@ -73,6 +76,46 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
   if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
+  return EQ_OK;
+}
+
+// Several receive vectors per channel matrix: Y [W][nsym][B], Z [W][nsym][U].
+// Tiles of up to symbol_tile(U) vectors per launch pair (equaliser + FP64
+// re-solve); every tile re-reads H.
+eq_status forward_sym(const eq_problem *p, bool fd, int32_t nsym, const eq_c32 *H, const eq_c32 *Y,
+                      const float *nu, eq_c32 *Z, float *s2, int32_t *info, void *ws, size_t ws_bytes,
+                      void *stream) {
+  eq_status st = check_problem(p);
+  if (st != EQ_OK) return st;
+  if (nsym < 1) return EQ_EINVAL;
+  if (nsym > EQ_MAX_SYM) return EQ_ENOTSUP;
+  if (p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
+  if (p->W == 0) return EQ_OK;
+  if (!H || !Y || !Z) return EQ_EINVAL;
+  if (!aligned(H, 8) || !aligned(Y, 8) || !aligned(Z, 8)) return EQ_EINVAL;
+  if ((s2 && !aligned(s2, 4)) || (info && !aligned(info, 4)) || (nu && !aligned(nu, 4))) return EQ_EINVAL;
+  if (!ws || ws_bytes < ws_bytes_for(p) || !aligned(ws, 4)) return EQ_EWORKSPACE;
+  FwdArgs a;
+  fill_fwd(a, p);
+  a.H = reinterpret_cast<const float2 *>(H);
+  a.nu = fd ? nu : nullptr;
+  a.s2 = s2;
+  a.info = info;
+  a.fb_count = reinterpret_cast<int32_t *>(ws);
+  a.fb_done = a.fb_count + 1;
+  a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
+  a.ysw = (int64_t)nsym * p->B;
+  a.zsw = (int64_t)nsym * p->U;
+  const int tile = symbol_tile(p->U);
+  const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int s0 = 0; s0 < nsym; s0 += tile) {
+    a.nsym = nsym - s0 < tile ? nsym - s0 : tile;
+    a.y = reinterpret_cast<const float2 *>(Y) + (size_t)s0 * p->B;
+    a.z = reinterpret_cast<float2 *>(Z) + (size_t)s0 * p->U;
+    if (launch_symbols(a, fd, prec, s) != hipSuccess) return EQ_EHIP;
+    if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
+  }
   return EQ_OK;
 }
 
@@ -182,6 +225,16 @@ eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z
 eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, const float *nu, eq_c32 *z,
                 float *sigma2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
   return forward(p, true, H, y, nu, z, sigma2, info, ws, ws_bytes, stream);
+}
+
+eq_status eq_pd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H, const eq_c32 *Y, eq_c32 *Z,
+                    float *sigma2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return forward_sym(p, false, nsym, H, Y, nullptr, Z, sigma2, info, ws, ws_bytes, stream);
+}
+
+eq_status eq_fd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H, const eq_c32 *Y, const float *nu,
+                    eq_c32 *Z, float *sigma2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return forward_sym(p, true, nsym, H, Y, nu, Z, sigma2, info, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

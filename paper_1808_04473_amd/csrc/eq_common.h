@@ -28,6 +28,12 @@ struct FwdArgs {
   int32_t W, B, U, C;
   float n0, rho, es;
   int32_t spw;          // FD: subcarriers per wave
+  // receive vectors: nsym per channel matrix in this launch (1 for the
+  // single-vector entry points), y + w*ysw is the first of subcarrier w,
+  // z + w*zsw its first estimate; vectors of one subcarrier are B (y) and
+  // U (z) elements apart
+  int32_t nsym;
+  int64_t ysw, zsw;
   uint16_t off[EQ_MAX_C + 1];
 };
 
@@ -54,6 +60,9 @@ hipError_t launch_forward(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 hipError_t launch_fp64_resolve(const FwdArgs &a, bool fd, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int n, hipStream_t s);
 hipError_t launch_probe_read(const void *buf, size_t bytes, float *sink, hipStream_t s);
+// several receive vectors per channel matrix: a.nsym <= symbol_tile(a.U)
+hipError_t launch_symbols(const FwdArgs &a, bool fd, int prec, hipStream_t s);
+int symbol_tile(int U);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);

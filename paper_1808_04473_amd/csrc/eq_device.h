@@ -315,22 +315,42 @@ __device__ __forceinline__ float2 slot_y(const Slot &b) {
   return make_float2(dpp<DPP_ROW_NEWBCAST + E>(b.yl.x), dpp<DPP_ROW_NEWBCAST + E>(b.yl.y));
 }
 
-// Streams the row blocks of a sequence of systems produced by gen (a
-// functor bool(SysRef &) returning false at the end of the sequence) with
-// the loads of the next two blocks in flight while body(slot) consumes the
-// current one; done(slot) follows the last block of each system, while the
-// next blocks' loads are still in flight.
-// Ring depth of the row-block stream: two blocks in flight while one is
-// consumed (a fourth slot measured no faster at either group width, and
-// spills in the refining forms).
-template <int UT>
-constexpr int stream_depth() {
-  return 3;
+// Three-slot ring over row blocks: issue(slot) starts the loads of the next
+// block (returning false once the stream is exhausted, after issuing the
+// same loads against empty descriptors), body(slot) consumes a block and
+// done(slot) follows the last block of each system.  Two blocks are in
+// flight while one is consumed (a fourth slot measured no faster at either
+// group width, and spills in the refining forms).  sched_barrier keeps each
+// block's loads where they are issued: the scheduler must not sink them into
+// (or hoist the consumer above) the previous block's arithmetic.
+template <class SlotT, class Issue, class Body, class Done>
+__device__ __forceinline__ void stream_ring3(Issue &issue, Body &body, Done &done) {
+  SlotT sa, sb, sc;
+  issue(sa);
+  bool vb = issue(sb);
+  while (true) {
+    const bool vc = issue(sc);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sa);
+    if (sa.last) done(sa);
+    if (!vb) break;
+    const bool va = issue(sa);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sb);
+    if (sb.last) done(sb);
+    if (!vc) break;
+    vb = issue(sb);
+    __builtin_amdgcn_sched_barrier(0);
+    body(sc);
+    if (sc.last) done(sc);
+    if (!va) break;
+  }
 }
 
+// Streams the row blocks of a sequence of systems produced by gen (a
+// functor bool(SysRef &) returning false at the end of the sequence).
 template <int UT, int AUX, class Gen, class Body, class Done>
 __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done) {
-  constexpr int DEPTH = stream_depth<UT>();
   constexpr int RPB = 8 * (64 / UT);
   SysRef cur;
   if (!gen(cur)) return;
@@ -362,75 +382,7 @@ __device__ __forceinline__ void stream_gen(int U, Gen &gen, Body body, Done done
     }
     return valid;
   };
-  // sched_barrier keeps each block's loads where they are issued: the
-  // scheduler must not sink them into (or hoist the consumer above) the
-  // previous block's arithmetic.
-  if constexpr (DEPTH == 4) {
-    // four-slot ring: three blocks in flight while one is consumed
-    Slot sa, sb, sc, sd;
-    issue(sa);
-    bool vb = issue(sb);
-    bool vc = issue(sc);
-    while (true) {
-      const bool vd = issue(sd);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sa);
-      if (sa.last) done(sa);
-      if (!vb) break;
-      const bool va = issue(sa);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sb);
-      if (sb.last) done(sb);
-      if (!vc) break;
-      vb = issue(sb);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sc);
-      if (sc.last) done(sc);
-      if (!vd) break;
-      vc = issue(sc);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sd);
-      if (sd.last) done(sd);
-      if (!va) break;
-    }
-  } else if constexpr (DEPTH == 3) {
-    Slot sa, sb, sc;
-    issue(sa);
-    bool vb = issue(sb);
-    while (true) {
-      const bool vc = issue(sc);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sa);
-      if (sa.last) done(sa);
-      if (!vb) break;
-      const bool va = issue(sa);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sb);
-      if (sb.last) done(sb);
-      if (!vc) break;
-      vb = issue(sb);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sc);
-      if (sc.last) done(sc);
-      if (!va) break;
-    }
-  } else {
-    // two-slot ring: one block in flight while the other is consumed
-    Slot sa, sb;
-    issue(sa);
-    while (true) {
-      const bool vb = issue(sb);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sa);
-      if (sa.last) done(sa);
-      if (!vb) break;
-      const bool va = issue(sa);
-      __builtin_amdgcn_sched_barrier(0);
-      body(sb);
-      if (sb.last) done(sb);
-      if (!va) break;
-    }
-  }
+  stream_ring3<Slot>(issue, body, done);
 }
 
 // Fixed list of systems 0..ns-1 described by seg(s, Hw, yw, r0, r1);
@@ -786,6 +738,24 @@ __device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, i
     inverse_columns<UT>(f, i);
   }
   return apply_xh<UT>(f, t);
+}
+
+// Factorises A (rows in f.a) and forms the columns of X = L^{-1} in f.x,
+// for systems whose right-hand sides come later (several per factor).
+// Returns 0 or the first bad pivot + 1.  With Ls (32-lane groups) L is
+// stored there and the inverse is formed from LDS, as in factor_solve.
+template <int UT>
+__device__ __forceinline__ int factor_inverse(Factor<UT> &f, int i, float2 (*Ls)[UT] = nullptr) {
+  const int fail = cholesky<UT>(f, i);
+  if (UT == 32 && Ls) {
+#pragma unroll
+    for (int k = 0; k < UT; ++k) lds_el<UT>(Ls, i, k) = k == i ? make_float2(f.dinv, 0.f) : f.a[k];
+    __syncthreads();
+    inverse_columns_lds<UT>(f, i, Ls);
+  } else {
+    inverse_columns<UT>(f, i);
+  }
+  return fail;
 }
 
 // A^{-1} b for lane-distributed b (lane i holds b_i); result at lane u.

@@ -20,27 +20,34 @@ __device__ __forceinline__ Dc dmulc(Dc a, Dc b) {  // a * conj(b)
 }
 __device__ __forceinline__ Dc dmul(Dc a, Dc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
+// Receive vectors per re-solve pass (the widest symbol tile).
+constexpr int kF64Sym = 32;
+
 struct F64Smem {
   Dc L[EQ_MAX_U][EQ_MAX_U + 1];
   Dc X[EQ_MAX_U][EQ_MAX_U + 1];  // X[j][u] = (L^{-1})_ju
   Dc m[EQ_MAX_U];
   Dc t[EQ_MAX_U];
+  Dc Z[kF64Sym][EQ_MAX_U];       // estimates (FD: weighted sums) per vector
   int fail;
 };
 
-// Re-solves one system.  Clusters c = 0..nclus-1 own rows off(c)..off(c+1)-1
-// (PD passes one cluster covering every row); nu_w = [C][U] user weights or
-// nullptr; on_info(c, fail) reports each cluster's FP64 pivot status.
+// Re-solves one system for nsym <= kF64Sym receive vectors (vector s at
+// yw + s * ys, its estimate at zw + s * zs).  Clusters c = 0..nclus-1 own rows
+// off(c)..off(c+1)-1 (PD passes one cluster covering every row); nu_w = [C][U]
+// user weights or nullptr; on_info(c, fail) reports each cluster's FP64 pivot
+// status.
 template <class Off, class Info>
 __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
                             int U, int nclus, Off off, double n0, double rho, bool fd,
-                            const float *nu_w, float2 *zw, float *s2w, Info on_info) {
+                            const float *nu_w, float2 *zw, float *s2w, Info on_info,
+                            int nsym, size_t ys, size_t zs) {
   const int tid = threadIdx.x;
-  double sw = 0.0, szx = 0.0, szy = 0.0, sv = 0.0;
+  double sw = 0.0, sv = 0.0;
   bool any_bad = false;
   for (int c = 0; c < nclus; ++c) {
     const int r0 = off(c), r1 = off(c + 1);
-    // Gram (lower triangle) + rho I and MRC
+    // Gram (lower triangle) + rho I
     for (int p = tid; p < U * U; p += 64) {
       const int i = p / U, j = p % U;
       if (j > i) continue;
@@ -52,15 +59,6 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
       }
       if (i == j) acc.x += rho;
       sm.L[i][j] = acc;
-    }
-    if (tid < U) {
-      Dc acc = {0.0, 0.0};
-      for (int b = r0; b < r1; ++b) {
-        const float2 h = Hw[(size_t)b * U + tid], yv = yw[b];
-        acc.x += (double)h.x * yv.x + (double)h.y * yv.y;
-        acc.y += (double)h.x * yv.y - (double)h.y * yv.x;
-      }
-      sm.m[tid] = acc;
     }
     if (tid == 0) sm.fail = 0;
     __syncthreads();
@@ -84,18 +82,7 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
       }
       __syncthreads();
     }
-    // t = L^{-1} m (thread 0) and the columns of L^{-1} (thread u)
-    if (tid == 0) {
-      for (int i = 0; i < U; ++i) {
-        Dc s = sm.m[i];
-        for (int k = 0; k < i; ++k) {
-          const Dc p = dmul(sm.L[i][k], sm.t[k]);
-          s.x -= p.x;
-          s.y -= p.y;
-        }
-        sm.t[i] = {s.x / sm.L[i][i].x, s.y / sm.L[i][i].x};
-      }
-    }
+    // the columns of L^{-1} (thread u)
     if (tid < U) {
       const int u = tid;
       for (int j = 0; j < U; ++j) {
@@ -109,51 +96,86 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
       }
     }
     __syncthreads();
+    // error variance and fusion weight of user u
+    double wgt = 1.0;
     if (tid < U) {
       const int u = tid;
       double d = 0.0;
-      Dc z = {0.0, 0.0};
-      for (int j = u; j < U; ++j) {
-        d += sm.X[j][u].x * sm.X[j][u].x + sm.X[j][u].y * sm.X[j][u].y;
-        z.x += sm.X[j][u].x * sm.t[j].x + sm.X[j][u].y * sm.t[j].y;  // conj(X_ju) t_j
-        z.y += sm.X[j][u].x * sm.t[j].y - sm.X[j][u].y * sm.t[j].x;
-      }
+      for (int j = u; j < U; ++j) d += sm.X[j][u].x * sm.X[j][u].x + sm.X[j][u].y * sm.X[j][u].y;
       const double s2 = n0 * d;
       if (fd) {
         if (nu_w) {
-          const double nu = nu_w[(size_t)c * U + u];
-          szx += nu * z.x;
-          szy += nu * z.y;
-          sv += nu * nu * s2;
+          wgt = nu_w[(size_t)c * U + u];
+          sv += wgt * wgt * s2;
         } else {
-          const double p = 1.0 / s2;
-          sw += p;
-          szx += p * z.x;
-          szy += p * z.y;
+          wgt = 1.0 / s2;
+          sw += wgt;
         }
       } else {
-        szx = z.x;
-        szy = z.y;
         sv = s2;
       }
       if (sm.fail) any_bad = true;
+    }
+    for (int s = 0; s < nsym; ++s) {
+      const float2 *ysv = yw + (size_t)s * ys;
+      // MRC of vector s
+      if (tid < U) {
+        Dc acc = {0.0, 0.0};
+        for (int b = r0; b < r1; ++b) {
+          const float2 h = Hw[(size_t)b * U + tid], yv = ysv[b];
+          acc.x += (double)h.x * yv.x + (double)h.y * yv.y;
+          acc.y += (double)h.x * yv.y - (double)h.y * yv.x;
+        }
+        sm.m[tid] = acc;
+      }
+      __syncthreads();
+      // t = L^{-1} m (thread 0)
+      if (tid == 0) {
+        for (int i = 0; i < U; ++i) {
+          Dc t = sm.m[i];
+          for (int k = 0; k < i; ++k) {
+            const Dc p = dmul(sm.L[i][k], sm.t[k]);
+            t.x -= p.x;
+            t.y -= p.y;
+          }
+          sm.t[i] = {t.x / sm.L[i][i].x, t.y / sm.L[i][i].x};
+        }
+      }
+      __syncthreads();
+      // z_u = sum_j conj(X_ju) t_j, weighted and summed over the clusters (FD)
+      if (tid < U) {
+        const int u = tid;
+        Dc z = {0.0, 0.0};
+        for (int j = u; j < U; ++j) {
+          z.x += sm.X[j][u].x * sm.t[j].x + sm.X[j][u].y * sm.t[j].y;
+          z.y += sm.X[j][u].x * sm.t[j].y - sm.X[j][u].y * sm.t[j].x;
+        }
+        if (fd) {
+          const Dc prev = c == 0 ? Dc{0.0, 0.0} : sm.Z[s][u];
+          sm.Z[s][u] = {prev.x + wgt * z.x, prev.y + wgt * z.y};
+        } else {
+          sm.Z[s][u] = z;
+        }
+      }
+      __syncthreads();
     }
     if (tid == 0) on_info(c, sm.fail);
     __syncthreads();
   }
   if (tid < U) {
-    double zx, zy, so;
-    if (fd && !nu_w) {
-      zx = szx / sw;
-      zy = szy / sw;
-      so = 1.0 / sw;
-    } else {
-      zx = szx;
-      zy = szy;
-      so = sv;
+    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+    const bool norm = fd && !nu_w;
+    for (int s = 0; s < nsym; ++s) {
+      double zx = sm.Z[s][tid].x, zy = sm.Z[s][tid].y;
+      if (norm) {
+        zx /= sw;
+        zy /= sw;
+      }
+      if (any_bad) zx = zy = nanv;
+      zw[(size_t)s * zs + tid] = make_float2((float)zx, (float)zy);
     }
-    if (any_bad) zx = zy = so = __longlong_as_double(0x7ff8000000000000ll);
-    zw[tid] = make_float2((float)zx, (float)zy);
+    double so = norm ? 1.0 / sw : sv;
+    if (any_bad) so = nanv;
     if (s2w) s2w[tid] = (float)so;
   }
   __syncthreads();
@@ -181,9 +203,10 @@ __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
       const size_t ii = FD ? (size_t)w * a.C + c : (size_t)w;
       a.info[ii] = fail | (a.info[ii] & EQ_INFO_FP64);
     };
-    fp64_system(sm, a.H + (size_t)w * HB, a.y + (size_t)w * a.B, a.U, FD ? a.C : 1, off,
+    fp64_system(sm, a.H + (size_t)w * HB, a.y + (size_t)w * a.ysw, a.U, FD ? a.C : 1, off,
                 (double)a.n0, rho, FD, a.nu ? a.nu + (size_t)w * a.C * a.U : nullptr,
-                a.z + (size_t)w * a.U, a.s2 ? a.s2 + (size_t)w * a.U : nullptr, info);
+                a.z + (size_t)w * a.zsw, a.s2 ? a.s2 + (size_t)w * a.U : nullptr, info, a.nsym,
+                (size_t)a.B, (size_t)a.U);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -210,7 +233,7 @@ __global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) 
     };
     fp64_system(sm, a.Hpool + d.h_off, a.ypool + d.y_off, d.U, FD ? d.C : 1, off, (double)d.n0,
                 (double)d.n0 / (double)a.es, FD, nullptr, a.zpool + d.z_off,
-                a.s2pool ? a.s2pool + d.z_off : nullptr, info);
+                a.s2pool ? a.s2pool + d.z_off : nullptr, info, 1, 0, 0);
     if (threadIdx.x == 0 && a.info) a.info[k] = worst | EQ_INFO_FP64;
   }
 }

@@ -1,0 +1,453 @@
+// Several receive vectors per channel matrix (Section VI-B).
+//
+// The OFDM symbols of one coherence interval share the channel, so the Gram
+// matrix of a subcarrier (PD) or cluster (FD) and its factor are formed once
+// and applied to every symbol; only the matched filter is formed per symbol.
+// The matched filters of a tile of up to UT symbols, H_c^H [y_1 .. y_S], are a
+// second MFMA product in the same pass over H: lane (g, j) of the streaming
+// layout loads rows 8g .. 8g+7 of receive vector j, which is the B operand
+// for the same K (row) index as the lane's H value is for the Gram.  H and
+// the receive vectors are each read from HBM once per tile.
+//
+// After the pass a lane group factors its system, forms X = L^{-1} and, for
+// each symbol, computes t = X m_s (rows of X read back from LDS) and
+// z_s = X^H t (columns of X in registers).  FD weights every cluster's
+// estimates with the weights of Lemma 1 (or given ones), which do not depend
+// on the symbol, and sums them over the clusters in cluster order.
+//
+// Forms: FP32 MFMA, and split-BF16 MFMA (three products per real product)
+// without refinement; the refining forms are not offered for several
+// symbols.  Ill-conditioned systems go to the FP64 re-solve queue as in the
+// single-vector kernels; the re-solve recomputes every symbol of the tile.
+#include "eq_round.h"
+
+namespace dbpeq {
+
+// ---------------------------------------------------------------- streaming
+// One row block: H as in the single-vector stream, and rows 8g .. 8g+7 of
+// receive vector j = lane % UT of the tile.
+struct SymSlot {
+  float2 h[8];
+  float2 y[8];
+  int s;
+  int nv;  // rows of this lane's group, from its first, inside the system
+  bool last;
+};
+
+template <int UT>
+struct SymLaneOff {
+  unsigned h;  // as LaneOff::h
+  unsigned y;  // (j B + 8 g) * 8 for symbols j < nsym, else out of range
+  int g;
+};
+
+template <int UT>
+__device__ __forceinline__ SymLaneOff<UT> sym_lane_offsets(int U, int B, int nsym) {
+  const int lane = lane_id();
+  const int col = lane % UT, g = lane / UT;
+  SymLaneOff<UT> o;
+  o.h = col < U ? (unsigned)((slot_row(0, g) * U + col) * 8) : kOutOfRange;
+  o.y = col < nsym ? (unsigned)(((unsigned)col * (unsigned)B + (unsigned)slot_row(0, g)) * 8u) : kOutOfRange;
+  o.g = g;
+  return o;
+}
+
+// Loads the row block at rb of rows [r0, r1) of H (row stride U) and of the
+// tile's receive vectors (vector stride B, Yw = vector 0 of the tile).  The Y
+// descriptor spans from row r0 of the first vector to row r1 of the last one:
+// rows past r1 of the other vectors are in range and are masked by nv when
+// the block is consumed.
+template <int UT>
+__device__ __forceinline__ void load_sym_slot(SymSlot &b, const SymLaneOff<UT> &lo, const float2 *__restrict__ Hw,
+                                              const float2 *__restrict__ Yw, int U, int B, int nsym, int rb,
+                                              int r0, int r1, bool live) {
+  const int nrow = live ? r1 - r0 : 0;
+  const int ylen = live ? ((nsym - 1) * B + (r1 - r0)) * 8 : 0;
+  const __amdgpu_buffer_rsrc_t rh =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(Hw + (size_t)r0 * U), (short)0, nrow * U * 8, kBufFlags);
+  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc((void *)(Yw + r0), (short)0, ylen, kBufFlags);
+  const unsigned rowb = (unsigned)((rb - r0) * U * 8);
+  const unsigned step = (unsigned)(U * 8);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2<kLoadLast>(rh, lo.h + rowb + e * step);
+  // one 8-byte load per row: a load is then either wholly inside the
+  // descriptor's range or wholly outside it
+  const unsigned yb = lo.y + (unsigned)((rb - r0) * 8);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) b.y[e] = buf_ld2<kLoadLast>(ry, yb + 8u * e);
+  b.nv = r1 - (rb + slot_row(0, lo.g));
+}
+
+// Matched-filter accumulators: Re / Im of H^H Y, element (u, j) at the
+// position acc_pos gives for (i, j).
+template <int UT> struct MAcc;
+template <> struct MAcc<16> { f4 re, im; };
+template <> struct MAcc<32> { f16v re, im; };
+
+template <int UT>
+__device__ __forceinline__ void macc_zero(MAcc<UT> &m) {
+  constexpr int NR = UT == 16 ? 4 : 16;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { m.re[r] = 0.f; m.im[r] = 0.f; }
+}
+
+// acc += real split of the block's H^H H; m += H^H Y of the block:
+//   Re M = Hr^T Yr + Hi^T Yi,   Im M = Hr^T Yi - Hi^T Yr.
+template <int UT, int PREC>
+__device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAcc<UT> &m) {
+  float2 y[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) y[e] = e < sl.nv ? sl.y[e] : make_float2(0.f, 0.f);
+  if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float2 h = sl.h[e];
+      acc.rr = mma32(h.x, h.x, acc.rr);
+      m.re = mma32(h.x, y[e].x, m.re);
+      acc.ri = mma32(h.x, h.y, acc.ri);
+      m.im = mma32(h.x, y[e].y, m.im);
+      acc.ii = mma32(h.y, h.y, acc.ii);
+      m.re = mma32(h.y, y[e].y, m.re);
+      m.im = mma32(h.y, -y[e].x, m.im);
+    }
+  } else {
+    static_assert(PREC == PREC_BF16X3_NR, "one-pass forms only");
+    bf8 rh, rl, ih, il, yrh, yrl, yih, yil, nrh, nrl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float2 h = sl.h[e];
+      rh[e] = (__bf16)h.x;
+      rl[e] = (__bf16)(h.x - (float)rh[e]);
+      ih[e] = (__bf16)h.y;
+      il[e] = (__bf16)(h.y - (float)ih[e]);
+      yrh[e] = (__bf16)y[e].x;
+      yrl[e] = (__bf16)(y[e].x - (float)yrh[e]);
+      yih[e] = (__bf16)y[e].y;
+      yil[e] = (__bf16)(y[e].y - (float)yih[e]);
+      // round-to-nearest-even is symmetric: the split of -yr is the negated split
+      nrh[e] = -yrh[e];
+      nrl[e] = -yrl[e];
+    }
+    acc.rr = mma16(rh, rl, acc.rr);
+    m.re = mma16(rh, yrl, m.re);
+    acc.ri = mma16(rh, il, acc.ri);
+    m.im = mma16(rh, yil, m.im);
+    acc.ii = mma16(ih, il, acc.ii);
+    m.re = mma16(rl, yrh, m.re);
+    acc.rr = mma16(rl, rh, acc.rr);
+    m.im = mma16(rl, yih, m.im);
+    acc.ri = mma16(rl, ih, acc.ri);
+    m.re = mma16(rh, yrh, m.re);
+    acc.ii = mma16(il, ih, acc.ii);
+    m.im = mma16(rh, yih, m.im);
+    acc.rr = mma16(rh, rh, acc.rr);
+    m.re = mma16(ih, yil, m.re);
+    acc.ri = mma16(rh, ih, acc.ri);
+    m.im = mma16(ih, nrl, m.im);
+    acc.ii = mma16(ih, ih, acc.ii);
+    m.re = mma16(il, yih, m.re);
+    m.im = mma16(il, nrh, m.im);
+    m.re = mma16(ih, yih, m.re);
+    m.im = mma16(ih, nrh, m.im);
+  }
+}
+
+// Gram + matched filters of systems 0..ns-1 (seg(s, Hw, Yw, r0, r1) as in
+// stream_blocks, Yw = vector 0 of the tile); done(s, acc, m) follows the last
+// block of system s while the next blocks' loads are in flight.
+template <int UT, int PREC, class Seg, class Done>
+__device__ __forceinline__ void gram_mf_stream(int ns, int U, int B, int nsym, Seg seg, Done done) {
+  constexpr int RPB = 8 * (64 / UT);
+  Acc<UT> acc;
+  acc_zero<UT>(acc);
+  MAcc<UT> m;
+  macc_zero<UT>(m);
+  const SymLaneOff<UT> lo = sym_lane_offsets<UT>(U, B, nsym);
+  SysRef cur;
+  seg(0, cur.Hw, cur.yw, cur.r0, cur.r1);
+  cur.s = 0;
+  int next = 1;
+  int crb = cur.r0;
+  bool more = true;
+  auto issue = [&](SymSlot &sl) -> bool {
+    const bool valid = more;
+    load_sym_slot<UT>(sl, lo, cur.Hw, cur.yw, U, B, nsym, crb, cur.r0, cur.r1, valid);
+    sl.s = cur.s;
+    sl.last = crb + RPB >= cur.r1;
+    if (valid) {
+      if (crb + RPB < cur.r1) {
+        crb += RPB;
+      } else if (next < ns) {
+        seg(next, cur.Hw, cur.yw, cur.r0, cur.r1);
+        cur.s = next++;
+        crb = cur.r0;
+      } else {
+        more = false;
+      }
+    }
+    return valid;
+  };
+  auto body = [&](const SymSlot &b) { gram_mf_blk<UT, PREC>(b, acc, m); };
+  auto fin = [&](const SymSlot &b) {
+    done(b.s, acc, m);
+    acc_zero<UT>(acc);
+    macc_zero<UT>(m);
+  };
+  stream_ring3<SymSlot>(issue, body, fin);
+}
+
+// ---------------------------------------------------------------- LDS staging
+// NS matrix slots: A (G + rho I, then X), the matched filters of the tile
+// (rows = symbols, padded by two entries so the MFMA-layout stores hit
+// distinct banks, slots offset by 8 banks so the groups' broadcast reads do
+// too), and per-group fusion terms (FD).
+template <int UT, int NSLOT>
+struct SymSmem {
+  static constexpr int NSYS = 64 / UT;
+  static constexpr int NS = NSLOT;
+  static constexpr int MROW = UT + 2;
+  static constexpr int MSLOT = UT * MROW + 4;
+  float2 A[NS][UT][UT];
+  float2 Mv[NS * MSLOT];
+  float2 F[NS][UT];
+  __device__ __forceinline__ float2 &m(int slot, int s, int u) { return Mv[slot * MSLOT + s * MROW + u]; }
+};
+
+template <int UT, class SM>
+__device__ __forceinline__ void store_msym(SM &sm, int slot, const MAcc<UT> &m) {
+  constexpr int NR = UT == 16 ? 4 : 16;
+  const int lane = lane_id();
+  sfor<NR>([&](auto R) {
+    constexpr int r = R;
+    int i, j;
+    acc_pos<UT>(lane, r, i, j);
+    sm.m(slot, j, i) = make_float2(m.re[r], m.im[r]);
+  });
+}
+
+// ---------------------------------------------------------------- solve
+template <int UT>
+struct SymSolve {
+  Factor<UT> f;
+  float2 xr[UT];  // row i of X (lane i)
+  float d;        // [A^{-1}]_ii
+  float norm1;
+  int fail;
+  bool bad;
+};
+
+// Loads row i of the slot's A, factors it, forms X = L^{-1} (columns in
+// f.x) and parks X in the slot so that lane i can read row i of it.
+template <int UT, class SM>
+__device__ __forceinline__ void sym_factor(SymSolve<UT> &r, SM &sm, int slot, int i, int U) {
+  bool bad = false;
+  float rowsum = 0.f;
+#pragma unroll
+  for (int k = 0; k < UT; ++k) {
+    r.f.a[k] = lds_el<UT>(sm.A[slot], i, k);
+    bad |= !finite2(r.f.a[k]);
+    rowsum += __builtin_amdgcn_sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
+  }
+  r.bad = gany<UT>(bad);
+  r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
+  r.fail = factor_inverse<UT>(r.f, i, SM::NS < SM::NSYS ? sm.A[slot] : nullptr);
+  r.d = inv_diag<UT>(r.f);
+  __syncthreads();
+  // row u of the slot holds column u of X: lds_el(A, u, k) = X_ku
+#pragma unroll
+  for (int k = 0; k < UT; ++k) lds_el<UT>(sm.A[slot], i, k) = r.f.x[k];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UT; ++u) r.xr[u] = lds_el<UT>(sm.A[slot], u, i);
+}
+
+// z_s = X^H (X m_s) at lane i for the matched filter m_s of the slot.
+template <int UT, class SM>
+__device__ __forceinline__ float2 sym_apply(const SymSolve<UT> &r, SM &sm, int slot, int s) {
+  float tx = 0.f, ty = 0.f;
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const float2 mv = sm.m(slot, s, u);
+    tx = fmaf(r.xr[u].x, mv.x, fmaf(-r.xr[u].y, mv.y, tx));
+    ty = fmaf(r.xr[u].x, mv.y, fmaf(r.xr[u].y, mv.x, ty));
+  }
+  return apply_xh<UT>(r.f, make_float2(tx, ty));
+}
+
+__device__ __forceinline__ void enqueue_fp64_sym(const FwdArgs &a, int w) {
+  const int pos = atomicAdd(a.fb_count, 1);
+  if (pos >= 0 && pos < a.W) a.fb_list[pos] = w;  // capacity W
+}
+
+// PD: systems w0 .. w0+nvalid-1, one per lane group.
+template <int UT, int PREC, class SM>
+__device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid, SM &sm) {
+  const int lane = lane_id();
+  const int g = lane / UT, i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+  auto seg = [&](int s, const float2 *&Hw, const float2 *&Yw, int &r0, int &r1) {
+    const size_t w = (size_t)w0 + s;
+    Hw = a.H + w * HB;
+    Yw = a.y + w * (size_t)a.ysw;
+    r0 = 0;
+    r1 = a.B;
+  };
+  gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
+    store_gram<UT>(sm.A[s], acc, a.rho);
+    store_msym<UT>(sm, s, m);
+  });
+  for (int s = nvalid; s < SM::NS; ++s) store_identity<UT>(sm.A[s]);
+  __syncthreads();
+
+  const int slot = slot_of<SM>(g);
+  const bool live = g < nvalid;
+  SymSolve<UT> r;
+  sym_factor<UT>(r, sm, slot, i, a.U);
+  const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
+  const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
+  const int w = w0 + g;
+  const float nanv = __int_as_float(0x7fc00000);
+  float2 *zw = a.z + (size_t)w * a.zsw;
+  for (int s = 0; s < a.nsym; ++s) {
+    const float2 z = sym_apply<UT>(r, sm, slot, s);
+    if (live && i < a.U) zw[(size_t)s * a.U + i] = r.bad ? make_float2(nanv, nanv) : z;
+  }
+  if (live) {
+    if (i < a.U && a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d;
+    if (i == 0) {
+      if (a.info) a.info[w] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
+      if (routed) enqueue_fp64_sym(a, w);
+    }
+  }
+}
+
+// FD: all clusters of subcarrier w, NSYS local systems per round.  Fusion
+// lane (q, u) = (lane / UT, lane % UT) holds the sums of user u for the
+// symbols q, q + NSYS, q + 2 NSYS, ...
+template <int UT, int PREC, class SM>
+__device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
+  constexpr int NSYS = 64 / UT;
+  constexpr int KS = UT / NSYS;  // symbols per fusion lane
+  const int lane = lane_id();
+  const int g = lane / UT, i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+  const int C = a.C;
+  const bool user_nu = a.nu != nullptr;
+  const float nanv = __int_as_float(0x7fc00000);
+  float2 zf[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) zf[k] = make_float2(0.f, 0.f);
+  float sw = 0.f, sv = 0.f;
+  bool routed_any = false;
+
+  for (int base = 0; base < C; base += NSYS) {
+    const int nvalid = min(NSYS, C - base);
+    auto seg = [&](int s, const float2 *&Hw, const float2 *&Yw, int &r0, int &r1) {
+      Hw = a.H + (size_t)w * HB;
+      Yw = a.y + (size_t)w * a.ysw;
+      r0 = a.off[base + s];
+      r1 = a.off[base + s + 1];
+    };
+    gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
+      store_gram<UT>(sm.A[s], acc, a.rho);
+      store_msym<UT>(sm, s, m);
+    });
+    for (int s = nvalid; s < NSYS; ++s) store_identity<UT>(sm.A[s]);
+    __syncthreads();
+
+    const int c = base + g;
+    const bool live = g < nvalid;
+    SymSolve<UT> r;
+    sym_factor<UT>(r, sm, g, i, a.U);
+    const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
+    const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
+    if (live && i == 0 && a.info) a.info[(size_t)w * C + c] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
+    routed_any |= __ballot(routed) != 0ull;
+    const float s2c = a.n0 * r.d;
+    float p = 0.f;
+    if (live && i < a.U) p = user_nu ? a.nu[((size_t)w * C + c) * a.U + i] : 1.0f / s2c;
+    // weighted estimates replace the group's matched filters, row by row
+    // (each row is read by the whole group before its lane i overwrites it)
+    for (int s = 0; s < a.nsym; ++s) {
+      const float2 z = sym_apply<UT>(r, sm, g, s);
+      sm.m(g, s, i) = r.bad ? make_float2(nanv, nanv) : make_float2(p * z.x, p * z.y);
+    }
+    sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
+    __syncthreads();
+    // fusion over the round's clusters, in cluster order
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int s = g + NSYS * k;
+      if (s < a.nsym) {
+        for (int q = 0; q < nvalid; ++q) {
+          const float2 v = sm.m(q, s, i);
+          zf[k].x += v.x;
+          zf[k].y += v.y;
+        }
+      }
+    }
+    for (int q = 0; q < nvalid; ++q) {
+      const float2 v = sm.F[q][i];
+      sw += v.x;
+      sv += v.y;
+    }
+    __syncthreads();
+  }
+
+  if (i < a.U) {
+    const float inv = 1.0f / sw;
+    float2 *zw = a.z + (size_t)w * a.zsw;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int s = g + NSYS * k;
+      if (s < a.nsym) zw[(size_t)s * a.U + i] = user_nu ? zf[k] : make_float2(zf[k].x * inv, zf[k].y * inv);
+    }
+    if (g == 0 && a.s2) a.s2[(size_t)w * a.U + i] = user_nu ? sv : inv;
+  }
+  if (lane == 0 && routed_any) enqueue_fp64_sym(a, w);
+}
+
+// PD systems per work item.
+template <int UT>
+constexpr int sym_pd_per() {
+  return UT == 32 ? 1 : 4;
+}
+
+// One wave per workgroup, one work item per workgroup.  The LDS staging
+// (about 17 KB UT = 16, 17 KB PD / 35 KB FD at UT = 32) bounds occupancy to
+// two waves per SIMD or fewer, which the register target matches.
+template <int UT, int PREC, bool FD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void eq_symbols_kernel(const FwdArgs a) {
+  __shared__ SymSmem<UT, FD ? 64 / UT : sym_pd_per<UT>()> sm;
+  if constexpr (FD) {
+    fd_sym_task<UT, PREC>(a, blockIdx.x, sm);
+  } else {
+    const int w0 = blockIdx.x * sym_pd_per<UT>();
+    pd_sym_task<UT, PREC>(a, w0, min(sym_pd_per<UT>(), a.W - w0), sm);
+  }
+}
+
+template <int UT, int PREC, bool FD>
+static hipError_t launch_sym_one(const FwdArgs &a, hipStream_t s) {
+  const int per = FD ? 1 : sym_pd_per<UT>();
+  const int grid = (a.W + per - 1) / per;
+  hipLaunchKernelGGL((eq_symbols_kernel<UT, PREC, FD>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int UT, bool FD>
+static hipError_t launch_sym_prec(const FwdArgs &a, int prec, hipStream_t s) {
+  return prec == PREC_FP32 ? launch_sym_one<UT, PREC_FP32, FD>(a, s) : launch_sym_one<UT, PREC_BF16X3_NR, FD>(a, s);
+}
+
+int symbol_tile(int U) { return ut_for(U); }
+
+hipError_t launch_symbols(const FwdArgs &a, bool fd, int prec, hipStream_t s) {
+  if (prec != PREC_FP32 && prec != PREC_BF16X3_NR) return hipErrorInvalidValue;
+  if (a.nsym < 1 || a.nsym > symbol_tile(a.U)) return hipErrorInvalidValue;
+  const int UT = ut_for(a.U);
+  if (UT == 16) return fd ? launch_sym_prec<16, true>(a, prec, s) : launch_sym_prec<16, false>(a, prec, s);
+  return fd ? launch_sym_prec<32, true>(a, prec, s) : launch_sym_prec<32, false>(a, prec, s);
+}
+
+}  // namespace dbpeq

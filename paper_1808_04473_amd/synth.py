@@ -126,6 +126,45 @@ def config_batch(cfg: int, snr_db: float | None = None, frame: int = 0,
     return make_batch(W or c["W"], c["B"], c["U"], c["C"], snr, c["mod"], seed)
 
 
+@dataclass
+class SymbolBatch:
+    """W channel matrices, each shared by S receive vectors (OFDM symbols of
+    one coherence interval): Y[w, s] = H[w] x[w, s] + n[w, s]."""
+
+    H: np.ndarray            # [W][B][U] complex64
+    Y: np.ndarray            # [W][S][B] complex64
+    x: np.ndarray            # [W][S][U] complex64 transmitted symbols
+    n0: float
+    cluster_off: np.ndarray  # [C+1] int32
+    es: float = 1.0
+
+
+def make_symbol_batch(W: int, B: int, U: int, C: int, S: int, snr_db: float, mod: str,
+                      seed: int, cluster_off=None) -> SymbolBatch:
+    """As make_batch, with S independent symbol vectors and noise draws per
+    channel matrix (formed in double precision, rounded to complex64)."""
+    rng = np.random.default_rng(seed)
+    H = _rayleigh(rng, (W, B, U), B)
+    pts = constellation(mod)
+    x = pts[rng.integers(0, len(pts), size=(W, S, U))]
+    n0 = noise_variance(U, B, snr_db)
+    sdn = math.sqrt(n0 / 2.0)
+    noise = (rng.standard_normal((W, S, B)) + 1j * rng.standard_normal((W, S, B))) * sdn
+    Y = np.matmul(x.astype(np.complex128), np.swapaxes(H.astype(np.complex128), 1, 2)) + noise
+    off = uniform_partition(B, C) if cluster_off is None else np.asarray(cluster_off, np.int32)
+    return SymbolBatch(H=H, Y=Y.astype(np.complex64), x=x.astype(np.complex64), n0=n0,
+                       cluster_off=off)
+
+
+def config_symbol_batch(cfg: int, nsym: int = 14, snr_db: float | None = None, frame: int = 0,
+                        W: int | None = None) -> SymbolBatch:
+    """Workload `cfg` with nsym OFDM symbols per channel matrix."""
+    c = CONFIGS[cfg]
+    snr = c["snrs"][0] if snr_db is None else snr_db
+    seed = BASE_SEED + 50 + cfg + 1000 * frame + int(round(snr * 7))
+    return make_symbol_batch(W or c["W"], c["B"], c["U"], c["C"], nsym, snr, c["mod"], seed)
+
+
 # ---------------------------------------------------------------------------
 # Ragged workload: thousands of independent systems of uneven shape.
 # ---------------------------------------------------------------------------

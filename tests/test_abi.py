@@ -153,3 +153,28 @@ def test_plan_validation(lib):
     assert lib.eq_plan_create(ct.byref(h), desc, 2, ps, 4, 0, 0, 1.0, None) == ENOTSUP
     assert lib.eq_plan_execute(None, A, A, A, A, A, None) == EINVAL
     assert lib.eq_plan_destroy(None) == 0
+
+
+def _call_sym(lib, prob, nsym, fd=False, H=A, Y=A, Z=A, ws=A, wsb=1 << 12):
+    if fd:
+        return lib.eq_fd_sym(ctypes.byref(prob), nsym, H, Y, None, Z, A, A, ws, wsb, None)
+    return lib.eq_pd_sym(ctypes.byref(prob), nsym, H, Y, Z, A, A, ws, wsb, None)
+
+
+@pytest.mark.parametrize("fd", [False, True])
+def test_symbols_validation(lib, fd):
+    # all rejected (or no-ops) before any HIP call
+    prob, _k = _prob()
+    assert _call_sym(lib, prob, 0, fd) == EINVAL
+    assert _call_sym(lib, prob, -3, fd) == EINVAL
+    assert _call_sym(lib, prob, 1025, fd) == ENOTSUP
+    assert _call_sym(lib, prob, 4, fd, Y=None) == EINVAL
+    assert _call_sym(lib, prob, 4, fd, Z=A + 4) == EINVAL
+    assert _call_sym(lib, prob, 4, fd, ws=None) == EWORKSPACE
+    for prec in (1, 2):  # refining forms are not offered for several vectors
+        p2, _k2 = _prob(prec=prec)
+        assert _call_sym(lib, p2, 4, fd) == ENOTSUP
+    p3, _k3 = _prob(n0=0.0)
+    assert _call_sym(lib, p3, 4, fd) == EINVAL
+    p0, _k0 = _prob(W=0)
+    assert _call_sym(lib, p0, 4, fd, H=None, Y=None, Z=None, ws=None, wsb=0) == 0

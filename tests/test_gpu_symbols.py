@@ -1,0 +1,167 @@
+"""GPU parity of eq_pd_sym / eq_fd_sym (several receive vectors per channel
+matrix, Section VI-B) against the FP64 oracle, element by element on the
+same seeded inputs, per receive vector: max over (w, s) of
+||z_ws - z_ref_ws||_inf / ||z_ref_ws||_inf <= 1e-4, sigma2 within 0.05 dB.
+
+Cases span several row blocks and a ragged tail (B not a multiple of the
+block rows, uneven clusters), symbol counts below, at and above one tile
+(16 vectors for U <= 16, 32 above), one vector, FD with given weights, a
+non-finite receive vector, the FP64 re-solve queue, and the launch size the
+benchmark times (sampled outputs plus properties of the whole batch)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_04473_amd import synth
+from gpu_util import TOL_DB, TOL_Z, dev, host, max_db_err, max_rel_err, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "bf16x3"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def run(mode, b, prec, nu=None, info=False):
+    from paper_1808_04473_amd import api
+    H, Y = dev(b.H), dev(b.Y)
+    if mode == "pd":
+        out = api.eq_pd_sym(H, Y, b.n0, b.cluster_off, precision=prec, return_info=info)
+    else:
+        out = api.eq_fd_sym(H, Y, b.n0, b.cluster_off, precision=prec, return_info=info,
+                            nu=None if nu is None else dev(nu.astype(np.float32)))
+    torch.cuda.synchronize()
+    return [host(t) for t in out]
+
+
+def ref(mode, b, nu=None):
+    if mode == "pd":
+        return oracle.eq_pd_symbols(b.H, b.Y, b.n0, b.cluster_off)
+    return oracle.eq_fd_symbols(b.H, b.Y, b.n0, b.cluster_off, nu=nu)
+
+
+def check(mode, b, prec, nu=None):
+    z, s2 = run(mode, b, prec, nu)
+    zr, sr = ref(mode, b, nu)
+    assert z.shape == zr.shape
+    ez, es = max_rel_err(z, zr), max_db_err(s2, sr)
+    print(f"{mode} {prec} W={b.H.shape[0]} B={b.H.shape[1]} U={b.H.shape[2]} S={b.Y.shape[1]} "
+          f"C={len(b.cluster_off) - 1}: z err {ez:.2e}, sigma2 {es:.4f} dB", flush=True)
+    assert ez <= TOL_Z[prec], ez
+    assert es <= TOL_DB, es
+
+
+# (W, B, U, C or offsets, S)
+SHAPES = [
+    (64, 32, 4, 2, 14),                      # the small workload, 14 symbols
+    (40, 256, 16, 8, 14),                    # the paper's B=256, C=8, U=16
+    (8, 1024, 32, 16, 14),                   # B=1024, C=16, U=32
+    (13, 37, 5, [0, 5, 20, 37], 3),          # ragged rows and clusters
+    (9, 100, 16, [0, 33, 34, 100], 16),      # exactly one tile, a one-row cluster
+    (7, 96, 12, 4, 17),                      # two tiles, ragged symbol tail
+    (5, 130, 24, [0, 60, 130], 40),          # U > 16: tiles of 32, tail of 8
+    (6, 48, 8, 3, 1),                        # one vector
+    (5, 64, 32, 2, 33),                      # full 32-user tile, two tiles
+]
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"W{s[0]}B{s[1]}U{s[2]}S{s[4]}")
+def test_symbols_match_oracle(mode, prec, shape):
+    W, B, U, C, S = shape
+    off = C if isinstance(C, list) else None
+    nc = len(C) - 1 if isinstance(C, list) else C
+    b = synth.make_symbol_batch(W, B, U, nc, S, 10.0, "16qam", seed=W * 1000 + B + S, cluster_off=off)
+    check(mode, b, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fd_symbols_given_weights(prec):
+    b = synth.make_symbol_batch(11, 96, 8, 3, 9, 5.0, "qpsk", seed=77)
+    nu = np.random.default_rng(5).uniform(0.1, 1.0, size=(11, 3, 8))
+    check("fd", b, prec, nu=nu)
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+def test_one_vector_equals_single_vector_call(mode):
+    """nsym = 1 gives what eq_pd / eq_fd give for the same y (both within
+    the gate of the oracle, and close to each other)."""
+    from paper_1808_04473_amd import api
+    b = synth.make_symbol_batch(50, 256, 16, 8, 1, 10.0, "16qam", seed=8)
+    z1, s1 = run(mode, b, "fp32")
+    H, y = dev(b.H), dev(b.Y[:, 0, :])
+    fn = api.eq_pd if mode == "pd" else api.eq_fd
+    z0, s0 = fn(H, y, b.n0, b.cluster_off)
+    torch.cuda.synchronize()
+    assert max_rel_err(z1[:, 0], host(z0)) <= 2e-5
+    assert max_db_err(s1, host(s0)) <= 1e-3
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+def test_non_finite_vector_stays_in_its_symbol(mode):
+    """A NaN in one receive vector gives NaN for that vector only: the
+    other vectors of the subcarrier, sigma2 and info are unaffected."""
+    b = synth.make_symbol_batch(6, 64, 8, 2, 5, 10.0, "qpsk", seed=9)
+    b.Y[2, 3, 17] = np.complex64(complex(np.nan, 0.0))
+    z, s2, info = run(mode, b, "fp32", info=True)
+    assert np.isnan(z[2, 3]).all()
+    keep = np.ones(z.shape[:2], bool)
+    keep[2, 3] = False
+    zr, sr = ref(mode, b)
+    assert max_rel_err(z[keep], zr[keep]) <= TOL_Z["fp32"]
+    assert max_db_err(s2, sr) <= TOL_DB
+    assert (info == 0).all()
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+def test_symbols_fp64_queue(mode):
+    """Nearly collinear users and a tiny N0: every subcarrier is routed to
+    the FP64 re-solve, which recomputes all vectors of every tile."""
+    rng = np.random.default_rng(12)
+    W, B, U, C, S = 40, 48, 4, 2, 20
+    b = synth.make_symbol_batch(W, B, U, C, S, 10.0, "qpsk", seed=13)
+    H = b.H.astype(np.complex128)
+    H[:, :, 1] = H[:, :, 0] + 1e-4 * (rng.standard_normal((W, B)) + 1j * rng.standard_normal((W, B)))
+    b.H = H.astype(np.complex64)
+    b.Y = np.matmul(b.x.astype(np.complex128), np.swapaxes(b.H.astype(np.complex128), 1, 2)).astype(np.complex64)
+    b.n0 = float(np.float32(1e-9))
+    z, s2, info = run(mode, b, "fp32", info=True)
+    flags = (info & (1 << 30)) != 0
+    routed = flags if mode == "pd" else flags.any(axis=1)
+    assert routed.all(), int(routed.sum())
+    zr, sr = ref(mode, b)
+    assert max_rel_err(z, zr) <= TOL_Z["fp32"]
+    assert max_db_err(s2, sr) <= TOL_DB
+
+
+def test_symbols_bench_launch_size():
+    """B=256, C=8, U=16 with 14 symbols at 38,400 subcarriers (32 frames of
+    1200), as timed: every output finite, info clear, sampled subcarriers
+    against the oracle."""
+    from paper_1808_04473_amd import api
+    frames = [synth.config_symbol_batch(2, 14, 10.0, frame=f) for f in range(32)]
+    Hn = np.concatenate([f.H for f in frames])
+    Yn = np.concatenate([f.Y for f in frames])
+    n0, off = frames[0].n0, frames[0].cluster_off
+    del frames
+    H, Y = dev(Hn), dev(Yn)
+    idx = np.unique(np.concatenate([[0, Hn.shape[0] - 1],
+                                    np.random.default_rng(4).choice(Hn.shape[0], 256, replace=False)]))
+    sel = torch.from_numpy(idx).to(H.device)
+    for mode in ("pd", "fd"):
+        for prec in PRECS:
+            fn = api.eq_pd_sym if mode == "pd" else api.eq_fd_sym
+            z, s2, info = fn(H, Y, n0, off, precision=prec, return_info=True)
+            torch.cuda.synchronize()
+            assert int(info.ne(0).sum().item()) == 0
+            assert bool(torch.isfinite(torch.view_as_real(z)).all().item())
+            assert bool((s2 > 0).all().item())
+            rf = oracle.eq_pd_symbols if mode == "pd" else oracle.eq_fd_symbols
+            zr, sr = rf(Hn[idx], Yn[idx], n0, off)
+            ez, es = max_rel_err(host(z[sel]), zr), max_db_err(host(s2[sel]), sr)
+            print(f"{mode} {prec} 38400 x 14: {len(idx)} sampled, z err {ez:.2e}, sigma2 {es:.4f} dB", flush=True)
+            assert ez <= TOL_Z[prec] and es <= TOL_DB
