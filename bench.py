@@ -118,11 +118,64 @@ def _rel_err(zg, zr):
     return float(np.max(np.max(np.abs(zg - zr), -1) / np.max(np.abs(zr), -1)))
 
 
+NSYM = 14  # OFDM symbols per coherence interval (Section VI-B)
+
+
+def bytes_per_system_sym(B, U, S):
+    """Algorithmic HBM bytes of one channel matrix with S receive vectors."""
+    return B * U * 8 + S * B * 8 + S * U * 8 + U * 4
+
+
+def symbol_inputs(Hn, S, seed=11):
+    from paper_1808_04473_amd import synth
+    Yn, _ = synth.symbols_for_channels(Hn, S, SNR_DB, "16qam", seed)
+    return Yn
+
+
+def symbol_measurements(Hn, n0, off, H, steps, S, tag):
+    """eq_pd_sym / eq_fd_sym with S receive vectors per channel matrix, both
+    one-pass forms, against S single-vector calls of the same form."""
+    import torch
+    import oracle
+    from paper_1808_04473_amd import api
+    dev = torch.device("cuda:0")
+    W, Bs, Us = Hn.shape
+    Hd = torch.from_numpy(Hn).to(dev) if H is None else H
+    Yn = symbol_inputs(Hn, S)
+    Y = torch.from_numpy(Yn).to(dev)
+    y1 = Y[:, 0, :].contiguous()
+    samp = np.arange(0, W, max(1, W // 48))
+    sel = torch.from_numpy(samp).to(dev)
+    nb = W * bytes_per_system_sym(Bs, Us, S)
+    out = {}
+    for mode in ("pd", "fd"):
+        fs = api.eq_pd_sym if mode == "pd" else api.eq_fd_sym
+        f1 = api.eq_pd if mode == "pd" else api.eq_fd
+        zr, sr = (oracle.eq_pd_symbols if mode == "pd" else oracle.eq_fd_symbols)(Hn[samp], Yn[samp], n0, off)
+        for prec in ("fp32", "bf16x3"):
+            t = _timed(lambda: fs(Hd, Y, n0, off, precision=prec), steps, 3)
+            t1 = _timed(lambda: f1(Hd, y1, n0, off, precision=prec), steps, 3)
+            z, s2 = fs(Hd, Y, n0, off, precision=prec)
+            t.update({"subcarriers_per_s": W / (t["call_ms_mean"] * 1e-3),
+                      "vectors_per_s": W * S / (t["call_ms_mean"] * 1e-3),
+                      "alg_GBps": nb / (t["call_ms_mean"] * 1e-3) / 1e9,
+                      "single_vector_call_ms_mean": t1["call_ms_mean"],
+                      "speedup_vs_single_vector_calls": S * t1["call_ms_mean"] / t["call_ms_mean"],
+                      "parity_max_rel_err_z": _rel_err(z[sel].cpu().numpy(), zr),
+                      "parity_max_sigma2_db": float(np.max(np.abs(10 * np.log10(s2[sel].cpu().numpy() / sr))))})
+            t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+            out[f"symbols{S}_{tag}_{mode}_{prec}"] = t
+            del z, s2
+    del Y, y1
+    return out
+
+
 def extra_measurements(Hn, yn, n0, off, H, y, steps):
     """The other rows of the path, each timed the same way and parity-sampled
     against the oracle: single-frame latency (W = 1200), the B = 1024 / U = 32
-    workload in every precision form, ragged batches of 4096 systems, and the
-    FD forward + adjoint of the differentiation workload."""
+    workload in every precision form, ragged batches of 4096 systems, 14
+    receive vectors per channel matrix, and the FD forward + adjoint of the
+    differentiation workload."""
     import torch
     import oracle
     from paper_1808_04473_amd import api, synth
@@ -190,6 +243,11 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
             pl.close()
     del pools
 
+    # several receive vectors per channel matrix: 14 OFDM symbols per subcarrier
+    # on the headline channels and on the B = 1024 / U = 32 channels
+    out.update(symbol_measurements(Hn, n0, off, H, steps, NSYM, "B256_U16"))
+    out.update(symbol_measurements(H3n, n03, off3, None, steps, NSYM, "B1024_U32"))
+
     # differentiation workload: FD forward + adjoint (w.r.t. H, y, N0), 38,400 systems
     gz = torch.randn(H.shape[0], U, dtype=torch.complex64, device=dev)
 
@@ -205,6 +263,24 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
     return out
 
 
+def symbols_main(args, dev):
+    """--nsym S: the headline channels with S receive vectors each, timed per
+    variant the same way (one JSON line; not the headline metric)."""
+    import torch
+    Hn, _, n0, off = make_inputs(args.frames)
+    W = Hn.shape[0]
+    H = torch.from_numpy(Hn).to(dev)
+    variants = [("pd", "fp32"), ("pd", "bf16x3"), ("fd", "fp32"), ("fd", "bf16x3")] \
+        if args.variants == "all" else [tuple(v.split(":")) for v in args.variants.split(",")]
+    r = symbol_measurements(Hn, n0, off, H, args.steps, args.nsym, "B256_U16")
+    res = {f"{m}_{p}": r[f"symbols{args.nsym}_B256_U16_{m}_{p}"] for m, p in variants}
+    print(json.dumps({"metric": f"equalized receive vectors/s @B={B},U={U},C={C},N_sym={args.nsym}",
+                      "unit": "receive vectors/s", "n_gpus": 1, "steps": args.steps,
+                      "config": {"workload": f"{W} subcarriers x {args.nsym} OFDM symbols, B={B}, C={C}, U={U}"},
+                      "variants": res}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +294,9 @@ def main(argv=None):
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (B=1024/U=32, ragged, adjoint, latency)")
+    ap.add_argument("--nsym", type=int, default=1,
+                    help="time eq_pd_sym / eq_fd_sym with this many receive vectors per channel "
+                         "matrix instead of the headline workload (for focused profiles)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -232,6 +311,9 @@ def main(argv=None):
     api.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.nsym > 1:
+        return symbols_main(args, dev)
 
     t_gen = time.perf_counter()
     Hn, yn, n0, off = make_inputs(args.frames)

@@ -9,14 +9,16 @@
 // for the same K (row) index as the lane's H value is for the Gram.  H and
 // the receive vectors are each read from HBM once per tile.
 //
-// After the pass a lane group factors its system, forms X = L^{-1} and, for
-// each symbol, computes t = X m_s (rows of X read back from LDS) and
-// z_s = X^H t (columns of X in registers).  FD weights every cluster's
+// After the pass a lane group factors its system and forms X = L^{-1}.
+// With 16 users the estimates of all symbols, Z = X^H (X M), are two
+// complex 16 x 16 x 16 products on FP32 MFMA per system; with 32 users each
+// lane group computes, per symbol, t = X m_s (rows of X read back from LDS)
+// and z_s = X^H t (columns of X in registers).  FD weights every cluster's
 // estimates with the weights of Lemma 1 (or given ones), which do not depend
 // on the symbol, and sums them over the clusters in cluster order.
 //
-// Forms: FP32 MFMA, and split-BF16 MFMA (three products per real product)
-// without refinement; the refining forms are not offered for several
+// Forms: FP32 MFMA (the matched filter as three real products), and
+// split-BF16 MFMA (three products per real product) without refinement; the refining forms are not offered for several
 // symbols.  Ill-conditioned systems go to the FP64 re-solve queue as in the
 // single-vector kernels; the re-solve recomputes every symbol of the tile.
 #include "eq_round.h"
@@ -71,28 +73,40 @@ __device__ __forceinline__ void load_sym_slot(SymSlot &b, const SymLaneOff<UT> &
 #pragma unroll
   for (int e = 0; e < 8; ++e) b.h[e] = buf_ld2<kLoadLast>(rh, lo.h + rowb + e * step);
   // one 8-byte load per row: a load is then either wholly inside the
-  // descriptor's range or wholly outside it
+  // descriptor's range or wholly outside it.  The eight loads of a lane read
+  // one 64-byte span, so consecutive loads share cache lines: these use the
+  // default policy (with the nontemporal one the lines were fetched from
+  // HBM again, 22-28% more bytes than the algorithm reads).
   const unsigned yb = lo.y + (unsigned)((rb - r0) * 8);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) b.y[e] = buf_ld2<kLoadLast>(ry, yb + 8u * e);
+  for (int e = 0; e < 8; ++e) b.y[e] = buf_ld2<kLoadKeep>(ry, yb + 8u * e);
   b.nv = r1 - (rb + slot_row(0, lo.g));
 }
 
-// Matched-filter accumulators: Re / Im of H^H Y, element (u, j) at the
-// position acc_pos gives for (i, j).
+// Matched-filter accumulators, element (u, j) at the position acc_pos gives
+// for (i, j).  FP32 forms the complex product H^H Y with three real MFMA
+// products (Gauss):
+//   k1 = (Hr - Hi)^T Yr,  k2 = Hr^T (Yi - Yr),  k3 = Hi^T (Yr + Yi),
+//   Re M = Hr^T Yr + Hi^T Yi = k1 + k3,   Im M = Hr^T Yi - Hi^T Yr = k1 + k2;
+// the split-BF16 form accumulates Re M in k1 and Im M in k2 directly.
 template <int UT> struct MAcc;
-template <> struct MAcc<16> { f4 re, im; };
-template <> struct MAcc<32> { f16v re, im; };
+template <> struct MAcc<16> { f4 k1, k2, k3; };
+template <> struct MAcc<32> { f16v k1, k2, k3; };
 
 template <int UT>
 __device__ __forceinline__ void macc_zero(MAcc<UT> &m) {
   constexpr int NR = UT == 16 ? 4 : 16;
 #pragma unroll
-  for (int r = 0; r < NR; ++r) { m.re[r] = 0.f; m.im[r] = 0.f; }
+  for (int r = 0; r < NR; ++r) { m.k1[r] = 0.f; m.k2[r] = 0.f; m.k3[r] = 0.f; }
 }
 
-// acc += real split of the block's H^H H; m += H^H Y of the block:
-//   Re M = Hr^T Yr + Hi^T Yi,   Im M = Hr^T Yi - Hi^T Yr.
+template <int PREC, int UT>
+__device__ __forceinline__ float2 macc_value(const MAcc<UT> &m, int r) {
+  if constexpr (PREC == PREC_FP32) return make_float2(m.k1[r] + m.k3[r], m.k1[r] + m.k2[r]);
+  else return make_float2(m.k1[r], m.k2[r]);
+}
+
+// acc += real split of the block's H^H H; m += H^H Y of the block.
 template <int UT, int PREC>
 __device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAcc<UT> &m) {
   float2 y[8];
@@ -103,12 +117,11 @@ __device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAc
     for (int e = 0; e < 8; ++e) {
       const float2 h = sl.h[e];
       acc.rr = mma32(h.x, h.x, acc.rr);
-      m.re = mma32(h.x, y[e].x, m.re);
+      m.k1 = mma32(h.x - h.y, y[e].x, m.k1);
       acc.ri = mma32(h.x, h.y, acc.ri);
-      m.im = mma32(h.x, y[e].y, m.im);
+      m.k2 = mma32(h.x, y[e].y - y[e].x, m.k2);
       acc.ii = mma32(h.y, h.y, acc.ii);
-      m.re = mma32(h.y, y[e].y, m.re);
-      m.im = mma32(h.y, -y[e].x, m.im);
+      m.k3 = mma32(h.y, y[e].x + y[e].y, m.k3);
     }
   } else {
     static_assert(PREC == PREC_BF16X3_NR, "one-pass forms only");
@@ -129,26 +142,26 @@ __device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAc
       nrl[e] = -yrl[e];
     }
     acc.rr = mma16(rh, rl, acc.rr);
-    m.re = mma16(rh, yrl, m.re);
+    m.k1 = mma16(rh, yrl, m.k1);
     acc.ri = mma16(rh, il, acc.ri);
-    m.im = mma16(rh, yil, m.im);
+    m.k2 = mma16(rh, yil, m.k2);
     acc.ii = mma16(ih, il, acc.ii);
-    m.re = mma16(rl, yrh, m.re);
+    m.k1 = mma16(rl, yrh, m.k1);
     acc.rr = mma16(rl, rh, acc.rr);
-    m.im = mma16(rl, yih, m.im);
+    m.k2 = mma16(rl, yih, m.k2);
     acc.ri = mma16(rl, ih, acc.ri);
-    m.re = mma16(rh, yrh, m.re);
+    m.k1 = mma16(rh, yrh, m.k1);
     acc.ii = mma16(il, ih, acc.ii);
-    m.im = mma16(rh, yih, m.im);
+    m.k2 = mma16(rh, yih, m.k2);
     acc.rr = mma16(rh, rh, acc.rr);
-    m.re = mma16(ih, yil, m.re);
+    m.k1 = mma16(ih, yil, m.k1);
     acc.ri = mma16(rh, ih, acc.ri);
-    m.im = mma16(ih, nrl, m.im);
+    m.k2 = mma16(ih, nrl, m.k2);
     acc.ii = mma16(ih, ih, acc.ii);
-    m.re = mma16(il, yih, m.re);
-    m.im = mma16(il, nrh, m.im);
-    m.re = mma16(ih, yih, m.re);
-    m.im = mma16(ih, nrh, m.im);
+    m.k1 = mma16(il, yih, m.k1);
+    m.k2 = mma16(il, nrh, m.k2);
+    m.k1 = mma16(ih, yih, m.k1);
+    m.k2 = mma16(ih, nrh, m.k2);
   }
 }
 
@@ -213,7 +226,7 @@ struct SymSmem {
   __device__ __forceinline__ float2 &m(int slot, int s, int u) { return Mv[slot * MSLOT + s * MROW + u]; }
 };
 
-template <int UT, class SM>
+template <int UT, int PREC, class SM>
 __device__ __forceinline__ void store_msym(SM &sm, int slot, const MAcc<UT> &m) {
   constexpr int NR = UT == 16 ? 4 : 16;
   const int lane = lane_id();
@@ -221,7 +234,7 @@ __device__ __forceinline__ void store_msym(SM &sm, int slot, const MAcc<UT> &m) 
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    sm.m(slot, j, i) = make_float2(m.re[r], m.im[r]);
+    sm.m(slot, j, i) = macc_value<PREC>(m, r);
   });
 }
 
@@ -229,7 +242,7 @@ __device__ __forceinline__ void store_msym(SM &sm, int slot, const MAcc<UT> &m) 
 template <int UT>
 struct SymSolve {
   Factor<UT> f;
-  float2 xr[UT];  // row i of X (lane i)
+  float2 xr[UT];  // row i of X (lane i; 32-lane groups only)
   float d;        // [A^{-1}]_ii
   float norm1;
   int fail;
@@ -237,7 +250,8 @@ struct SymSolve {
 };
 
 // Loads row i of the slot's A, factors it, forms X = L^{-1} (columns in
-// f.x) and parks X in the slot so that lane i can read row i of it.
+// f.x) and parks X in the slot (row u holds column u); 32-lane groups then
+// read row i of X back.
 template <int UT, class SM>
 __device__ __forceinline__ void sym_factor(SymSolve<UT> &r, SM &sm, int slot, int i, int U) {
   bool bad = false;
@@ -257,8 +271,61 @@ __device__ __forceinline__ void sym_factor(SymSolve<UT> &r, SM &sm, int slot, in
 #pragma unroll
   for (int k = 0; k < UT; ++k) lds_el<UT>(sm.A[slot], i, k) = r.f.x[k];
   __syncthreads();
+  if constexpr (UT == 32) {
 #pragma unroll
-  for (int u = 0; u < UT; ++u) r.xr[u] = lds_el<UT>(sm.A[slot], u, i);
+    for (int u = 0; u < UT; ++u) r.xr[u] = lds_el<UT>(sm.A[slot], u, i);
+  }
+}
+
+// 16 x 16 systems: Z = X^H (X M) for the slot's system and the tile's
+// symbols on FP32 MFMA (16x16x4), the whole wave on one system.  Each complex
+// product takes three real products (Gauss).  X comes from the slot (row u
+// holds column u of X), M from its matched-filter rows, which T = X M then
+// replaces.  On return lane (kk, c) = (lane / 16, lane % 16) holds
+// Z[4 kk + r][c] in (zr[r], zi[r]), r = 0..3: four users of symbol c.
+template <class SM>
+__device__ __forceinline__ void sym_mfma16(SM &sm, int slot, f4 &zr, f4 &zi) {
+  const int lane = lane_id();
+  const int kk = lane >> 4, c = lane & 15;
+  f4 k1, k2, k3;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) { k1[r] = 0.f; k2[r] = 0.f; k3[r] = 0.f; }
+  // T = X M: operand A[c][u] = X_cu, B[u][c] = M[u][c] (u = 4q + kk);
+  //   Re T = k1 - k3, Im T = k1 + k2 with k1 = (Xr + Xi) Mr,
+  //   k2 = Xr (Mi - Mr), k3 = Xi (Mr + Mi)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = 4 * q + kk;
+    const float2 x = lds_el<16>(sm.A[slot], u, c);
+    const float2 mv = sm.m(slot, c, u);
+    k1 = mma32(x.x + x.y, mv.x, k1);
+    k2 = mma32(x.x, mv.y - mv.x, k2);
+    k3 = mma32(x.y, mv.x + mv.y, k3);
+  }
+  // T replaces M (the wave's LDS accesses are performed in order, so every
+  // read of M above precedes these writes)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sm.m(slot, c, 4 * kk + r) = make_float2(k1[r] - k3[r], k1[r] + k2[r]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) { k1[r] = 0.f; k2[r] = 0.f; k3[r] = 0.f; }
+  // Z = X^H T: operand A[c][i] = conj(X_ic), B[i][c] = T[i][c] (i = 4q + kk);
+  //   Re Z = k1 + k3, Im Z = k1 + k2 with k1 = (Xr - Xi) Tr,
+  //   k2 = Xr (Ti - Tr), k3 = Xi (Tr + Ti)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * q + kk;
+    const float2 x = lds_el<16>(sm.A[slot], c, i);
+    const float2 tv = sm.m(slot, c, i);
+    k1 = mma32(x.x - x.y, tv.x, k1);
+    k2 = mma32(x.x, tv.y - tv.x, k2);
+    k3 = mma32(x.y, tv.x + tv.y, k3);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    zr[r] = k1[r] + k3[r];
+    zi[r] = k1[r] + k2[r];
+  }
 }
 
 // z_s = X^H (X m_s) at lane i for the matched filter m_s of the slot.
@@ -294,7 +361,7 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
   };
   gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
     store_gram<UT>(sm.A[s], acc, a.rho);
-    store_msym<UT>(sm, s, m);
+    store_msym<UT, PREC>(sm, s, m);
   });
   for (int s = nvalid; s < SM::NS; ++s) store_identity<UT>(sm.A[s]);
   __syncthreads();
@@ -307,10 +374,27 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
   const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
   const int w = w0 + g;
   const float nanv = __int_as_float(0x7fc00000);
-  float2 *zw = a.z + (size_t)w * a.zsw;
-  for (int s = 0; s < a.nsym; ++s) {
-    const float2 z = sym_apply<UT>(r, sm, slot, s);
-    if (live && i < a.U) zw[(size_t)s * a.U + i] = r.bad ? make_float2(nanv, nanv) : z;
+  if constexpr (UT == 16) {
+    // one system at a time on MFMA; slot q holds system w0 + q
+    const unsigned long long badm = __ballot(r.bad);
+    const int kk = lane >> 4, c = lane & 15;
+    for (int q = 0; q < nvalid; ++q) {
+      f4 zr, zi;
+      sym_mfma16(sm, q, zr, zi);
+      const bool bq = (badm >> (16 * q)) & 1ull;
+      float2 *zw = a.z + (size_t)(w0 + q) * a.zsw + (size_t)c * a.U;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int u = 4 * kk + rr;
+        if (c < a.nsym && u < a.U) zw[u] = bq ? make_float2(nanv, nanv) : make_float2(zr[rr], zi[rr]);
+      }
+    }
+  } else {
+    float2 *zw = a.z + (size_t)w * a.zsw;
+    for (int s = 0; s < a.nsym; ++s) {
+      const float2 z = sym_apply<UT>(r, sm, slot, s);
+      if (live && i < a.U) zw[(size_t)s * a.U + i] = r.bad ? make_float2(nanv, nanv) : z;
+    }
   }
   if (live) {
     if (i < a.U && a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d;
@@ -321,13 +405,16 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
   }
 }
 
-// FD: all clusters of subcarrier w, NSYS local systems per round.  Fusion
-// lane (q, u) = (lane / UT, lane % UT) holds the sums of user u for the
-// symbols q, q + NSYS, q + 2 NSYS, ...
+// FD: all clusters of subcarrier w, NSYS local systems per round.  The
+// fusion sums (eq. (fusionrule)) run over the clusters in cluster order.
+// 16-lane groups: Z of each cluster comes from MFMA in accumulator layout,
+// and lane (kk, c) keeps the sums of users 4 kk + r of symbol c.  32-lane
+// groups: lane (q, u) = (lane / UT, lane % UT) keeps the sums of user u for
+// the symbols q, q + NSYS, q + 2 NSYS, ...
 template <int UT, int PREC, class SM>
 __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
   constexpr int NSYS = 64 / UT;
-  constexpr int KS = UT / NSYS;  // symbols per fusion lane
+  constexpr int KS = UT == 16 ? 4 : UT / NSYS;  // sums per lane
   const int lane = lane_id();
   const int g = lane / UT, i = lane % UT;
   const size_t HB = (size_t)a.B * a.U;
@@ -335,9 +422,11 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
   const bool user_nu = a.nu != nullptr;
   const float nanv = __int_as_float(0x7fc00000);
   float2 zf[KS];
+  float swk[UT == 16 ? 4 : 1], svk[UT == 16 ? 4 : 1];
 #pragma unroll
   for (int k = 0; k < KS; ++k) zf[k] = make_float2(0.f, 0.f);
-  float sw = 0.f, sv = 0.f;
+#pragma unroll
+  for (int k = 0; k < (UT == 16 ? 4 : 1); ++k) { swk[k] = 0.f; svk[k] = 0.f; }
   bool routed_any = false;
 
   for (int base = 0; base < C; base += NSYS) {
@@ -350,7 +439,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
     };
     gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
       store_gram<UT>(sm.A[s], acc, a.rho);
-      store_msym<UT>(sm, s, m);
+      store_msym<UT, PREC>(sm, s, m);
     });
     for (int s = nvalid; s < NSYS; ++s) store_identity<UT>(sm.A[s]);
     __syncthreads();
@@ -366,43 +455,72 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
     const float s2c = a.n0 * r.d;
     float p = 0.f;
     if (live && i < a.U) p = user_nu ? a.nu[((size_t)w * C + c) * a.U + i] : 1.0f / s2c;
-    // weighted estimates replace the group's matched filters, row by row
-    // (each row is read by the whole group before its lane i overwrites it)
-    for (int s = 0; s < a.nsym; ++s) {
-      const float2 z = sym_apply<UT>(r, sm, g, s);
-      sm.m(g, s, i) = r.bad ? make_float2(nanv, nanv) : make_float2(p * z.x, p * z.y);
-    }
-    sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
-    __syncthreads();
-    // fusion over the round's clusters, in cluster order
+    if constexpr (UT == 16) {
+      // weight and variance term of (cluster g, user i)
+      sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
+      __syncthreads();
+      const int kk = lane >> 4, cs = lane & 15;
+      for (int q = 0; q < nvalid; ++q) {
+        f4 zr, zi;
+        sym_mfma16(sm, q, zr, zi);
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-      const int s = g + NSYS * k;
-      if (s < a.nsym) {
-        for (int q = 0; q < nvalid; ++q) {
-          const float2 v = sm.m(q, s, i);
-          zf[k].x += v.x;
-          zf[k].y += v.y;
+        for (int rr = 0; rr < 4; ++rr) {
+          const float2 fv = sm.F[q][4 * kk + rr];
+          zf[rr].x += fv.x * zr[rr];
+          zf[rr].y += fv.x * zi[rr];
+          swk[rr] += fv.x;
+          svk[rr] += fv.y;
         }
       }
-    }
-    for (int q = 0; q < nvalid; ++q) {
-      const float2 v = sm.F[q][i];
-      sw += v.x;
-      sv += v.y;
+      (void)cs;
+    } else {
+      // weighted estimates replace the group's matched filters, row by row
+      // (each row is read by the whole group before its lane i overwrites it)
+      for (int s = 0; s < a.nsym; ++s) {
+        const float2 z = sym_apply<UT>(r, sm, g, s);
+        sm.m(g, s, i) = r.bad ? make_float2(nanv, nanv) : make_float2(p * z.x, p * z.y);
+      }
+      sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const int s = g + NSYS * k;
+        if (s < a.nsym) {
+          for (int q = 0; q < nvalid; ++q) {
+            const float2 v = sm.m(q, s, i);
+            zf[k].x += v.x;
+            zf[k].y += v.y;
+          }
+        }
+      }
+      for (int q = 0; q < nvalid; ++q) {
+        const float2 v = sm.F[q][i];
+        swk[0] += v.x;
+        svk[0] += v.y;
+      }
     }
     __syncthreads();
   }
 
-  if (i < a.U) {
-    const float inv = 1.0f / sw;
-    float2 *zw = a.z + (size_t)w * a.zsw;
+  float2 *zw = a.z + (size_t)w * a.zsw;
+  if constexpr (UT == 16) {
+    const int kk = lane >> 4, cs = lane & 15;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int u = 4 * kk + rr;
+      const float inv = 1.0f / swk[rr];
+      if (cs < a.nsym && u < a.U)
+        zw[(size_t)cs * a.U + u] = user_nu ? zf[rr] : make_float2(zf[rr].x * inv, zf[rr].y * inv);
+      if (cs == 0 && u < a.U && a.s2) a.s2[(size_t)w * a.U + u] = user_nu ? svk[rr] : inv;
+    }
+  } else if (i < a.U) {
+    const float inv = 1.0f / swk[0];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int s = g + NSYS * k;
       if (s < a.nsym) zw[(size_t)s * a.U + i] = user_nu ? zf[k] : make_float2(zf[k].x * inv, zf[k].y * inv);
     }
-    if (g == 0 && a.s2) a.s2[(size_t)w * a.U + i] = user_nu ? sv : inv;
+    if (g == 0 && a.s2) a.s2[(size_t)w * a.U + i] = user_nu ? svk[0] : inv;
   }
   if (lane == 0 && routed_any) enqueue_fp64_sym(a, w);
 }

@@ -156,6 +156,20 @@ def make_symbol_batch(W: int, B: int, U: int, C: int, S: int, snr_db: float, mod
                        cluster_off=off)
 
 
+def symbols_for_channels(H: np.ndarray, S: int, snr_db: float, mod: str, seed: int):
+    """S receive vectors per given channel matrix: (Y [W][S][B], x [W][S][U]),
+    Y = H x + n in complex64 arithmetic (for large throughput workloads)."""
+    W, B, U = H.shape
+    rng = np.random.default_rng(seed)
+    pts = constellation(mod).astype(np.complex64)
+    x = pts[rng.integers(0, len(pts), size=(W, S, U))]
+    sdn = np.float32(math.sqrt(noise_variance(U, B, snr_db) / 2.0))
+    Y = np.matmul(x, np.swapaxes(H, 1, 2))
+    Y.real += rng.standard_normal((W, S, B), dtype=np.float32) * sdn
+    Y.imag += rng.standard_normal((W, S, B), dtype=np.float32) * sdn
+    return np.ascontiguousarray(Y, dtype=np.complex64), x
+
+
 def config_symbol_batch(cfg: int, nsym: int = 14, snr_db: float | None = None, frame: int = 0,
                         W: int | None = None) -> SymbolBatch:
     """Workload `cfg` with nsym OFDM symbols per channel matrix."""
