@@ -15,6 +15,7 @@ Modules
 -------
 lmmse        forward PD / FD L-MMSE (Sections II-C, III-A, IV-A, IV-B), also with
              several receive vectors per channel matrix (Section VI-B)
+linear       PD / FD MRC and ZF (Section III-A, Section IV-A)
 adjoint      analytic gradients of both equalisers (derived, not in the paper)
 asymptotics  large-system SINR closed forms (Theorem 1, Corollary 1, Lemma 5)
 
@@ -26,6 +27,8 @@ unpinned".
 from .lmmse import (local_statistics, lmmse_estimate, lmmse_error_variance,
                     lmmse_error_variance_simplified, cond_estimate, eq_pd, eq_fd,
                     optimal_fusion_weights, eq_centralized, eq_pd_symbols, eq_fd_symbols)
+from .linear import (mrc_estimate, mrc_error_variance, zf_estimate, zf_error_variance,
+                     eq_pd_linear, eq_fd_linear)
 from .adjoint import pd_backward, fd_backward
 from .asymptotics import (sinr_pd_lmmse, sinr_fd_lmmse, tse_hanly_lmmse_sigma2)
 
@@ -33,6 +36,8 @@ __all__ = [
     "local_statistics", "lmmse_estimate", "lmmse_error_variance",
     "lmmse_error_variance_simplified", "cond_estimate", "eq_pd", "eq_fd",
     "optimal_fusion_weights", "eq_centralized", "eq_pd_symbols", "eq_fd_symbols",
+    "mrc_estimate", "mrc_error_variance", "zf_estimate", "zf_error_variance",
+    "eq_pd_linear", "eq_fd_linear",
     "pd_backward", "fd_backward",
     "sinr_pd_lmmse", "sinr_fd_lmmse", "tse_hanly_lmmse_sigma2",
 ]
