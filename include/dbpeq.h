@@ -25,7 +25,8 @@
  * reported per system in `info`:
  *     0            success
  *     k > 0        leading minor k of (G + rho I) not positive definite even
- *                  after the FP64 re-solve; that system's outputs are NaN
+ *                  after the FP64 re-solve (MRC: G_kk <= 0 for user k-1);
+ *                  that system's outputs are NaN
  *    -1            a non-finite value in the system's H or y; outputs NaN
  *   | EQ_INFO_FP64 (bit 30) the system (PD) or cluster (FD) had an estimated
  *                  condition number above EQ_COND_LIMIT or a failed FP32/BF16
@@ -44,7 +45,7 @@
 extern "C" {
 #endif
 
-#define EQ_ABI_VERSION 1
+#define EQ_ABI_VERSION 2
 #define EQ_MAX_U 32          /* users per system */
 #define EQ_MAX_B 65535       /* antennas per system */
 #define EQ_MAX_C 1024        /* clusters per system */
@@ -78,6 +79,21 @@ typedef enum {
   EQ_BF16X3 = 3
 } eq_precision;
 
+/* Equaliser of the forward calls (Section III-A; each FD cluster applies it
+   to its own statistics, Section IV-A):
+     EQ_LMMSE  z = (G + rho I)^{-1} y^MRC,  sigma2 = N0 diag((G + rho I)^{-1})
+     EQ_ZF     z = G^{-1} y^MRC,            sigma2 = N0 diag(G^{-1})
+               (needs B >= U for PD and every B_c >= U for FD; otherwise G is
+               singular: the system fails an FP32 pivot or the condition
+               check and is re-solved in FP64, and its outputs are NaN with
+               the pivot in info where the FP64 factorisation fails as well)
+     EQ_MRC    z = diag(G)^{-1} y^MRC,
+               sigma2_u = N0 / G_uu + E_s sum_{k != u} |G_uk|^2 / G_uu^2
+               (the diagonal of the Section III-A MRC variance); no
+               factorisation and no FP64 re-solve; EQ_FP32 or EQ_BF16X3 only.
+   The backward calls and the ragged plans are L-MMSE only. */
+typedef enum { EQ_LMMSE = 0, EQ_ZF = 1, EQ_MRC = 2 } eq_equalizer;
+
 /* Shared description of a batch of W systems. */
 typedef struct {
   int32_t W;                  /* systems in the batch, >= 0 (0 = no-op)          */
@@ -89,6 +105,7 @@ typedef struct {
   float n0;                   /* noise variance per complex entry, finite, > 0   */
   float es;                   /* symbol energy E_s, finite, > 0 (normally 1)     */
   int32_t precision;          /* an eq_precision value                            */
+  int32_t equalizer;          /* an eq_equalizer value (0 = L-MMSE)              */
 } eq_problem;
 
 /* Bytes of device workspace the forward calls need for this problem (the

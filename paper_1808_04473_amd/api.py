@@ -34,7 +34,7 @@ class EqError(RuntimeError):
 class EqProblem(ctypes.Structure):
     _fields_ = [("W", c_int32), ("B", c_int32), ("U", c_int32), ("C", c_int32),
                 ("cluster_off", POINTER(c_int32)), ("n0", c_float), ("es", c_float),
-                ("precision", c_int32)]
+                ("precision", c_int32), ("equalizer", c_int32)]
 
 
 class EqSys(ctypes.Structure):
@@ -104,12 +104,16 @@ def _check(fn: str, st: int):
         raise EqError(fn, st)
 
 
-def make_problem(W, B, U, cluster_off, n0, es=1.0, precision="fp32"):
+EQUALIZERS = {"lmmse": 0, "zf": 1, "mrc": 2}
+
+
+def make_problem(W, B, U, cluster_off, n0, es=1.0, precision="fp32", equalizer="lmmse"):
     """EqProblem plus the host offset array that must outlive the call."""
     off = np.ascontiguousarray(np.asarray(cluster_off, dtype=np.int32))
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    eqz = EQUALIZERS[equalizer] if isinstance(equalizer, str) else int(equalizer)
     p = EqProblem(int(W), int(B), int(U), int(len(off) - 1),
-                  off.ctypes.data_as(POINTER(c_int32)), float(n0), float(es), prec)
+                  off.ctypes.data_as(POINTER(c_int32)), float(n0), float(es), prec, eqz)
     return p, off
 
 
@@ -150,14 +154,15 @@ def _cached_workspace(prob: EqProblem, device) -> torch.Tensor:
 
 
 def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
-          ws=None):
-    """Partially decentralised L-MMSE of W systems: (z [W][U] c64, sigma2 [W][U] f32).
+          ws=None, equalizer="lmmse"):
+    """Partially decentralised equalisation of W systems (L-MMSE by default,
+    or equalizer="zf" / "mrc"): (z [W][U] c64, sigma2 [W][U] f32).
 
     `out` = (z, sigma2, info) and `ws` (uint8 workspace) may be preallocated."""
     lib = load_library()
     H, y = _check_inputs(H, y)
     W, B, U = H.shape
-    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
     if out is None:
         z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
         s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
@@ -172,12 +177,13 @@ def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, ou
 
 
 def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
-          out=None, ws=None):
-    """Fully decentralised L-MMSE; nu [W][C][U] float32 user weights or None (optimal)."""
+          out=None, ws=None, equalizer="lmmse"):
+    """Fully decentralised equalisation (L-MMSE, "zf" or "mrc" per cluster);
+    nu [W][C][U] float32 user weights or None (optimal)."""
     lib = load_library()
     H, y = _check_inputs(H, y)
     W, B, U = H.shape
-    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
     C = prob.C
     if nu is not None:
         if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
@@ -208,12 +214,12 @@ def _check_sym_inputs(H, Y):
     return H.contiguous(), Y.contiguous()
 
 
-def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws):
+def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws, equalizer):
     lib = load_library()
     H, Y = _check_sym_inputs(H, Y)
     W, B, U = H.shape
     S = Y.shape[1]
-    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
     C = prob.C
     if nu is not None:
         if not fd:
@@ -239,16 +245,16 @@ def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws
 
 
 def eq_pd_sym(H, Y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
-              ws=None):
-    """PD L-MMSE of S receive vectors per channel matrix: H [W][B][U], Y [W][S][B]
-    -> (Z [W][S][U] c64, sigma2 [W][U] f32).  Precision "fp32" or "bf16x3"."""
-    return _sym_call(False, H, Y, n0, cluster_off, None, precision, es, return_info, out, ws)
+              ws=None, equalizer="lmmse"):
+    """PD L-MMSE (or "zf") of S receive vectors per channel matrix: H [W][B][U],
+    Y [W][S][B] -> (Z [W][S][U] c64, sigma2 [W][U] f32).  Precision "fp32" or "bf16x3"."""
+    return _sym_call(False, H, Y, n0, cluster_off, None, precision, es, return_info, out, ws, equalizer)
 
 
 def eq_fd_sym(H, Y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
-              out=None, ws=None):
-    """FD L-MMSE of S receive vectors per channel matrix (weights as eq_fd)."""
-    return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws)
+              out=None, ws=None, equalizer="lmmse"):
+    """FD L-MMSE (or "zf") of S receive vectors per channel matrix (weights as eq_fd)."""
+    return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws, equalizer)
 
 
 def _bwd_workspace(prob: EqProblem, device) -> torch.Tensor:

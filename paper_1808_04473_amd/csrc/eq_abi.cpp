@@ -26,6 +26,8 @@ eq_status check_problem(const eq_problem *p) {
   if (!isfinite(p->n0) || !(p->n0 > 0.f)) return EQ_EINVAL;
   if (!isfinite(p->es) || !(p->es > 0.f)) return EQ_EINVAL;
   if (p->precision < EQ_FP32 || p->precision > EQ_BF16X3) return EQ_EINVAL;
+  if (p->equalizer < EQ_LMMSE || p->equalizer > EQ_MRC) return EQ_EINVAL;
+  if (p->equalizer == EQ_MRC && p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
   const float rho = p->n0 / p->es;
   if (!isfinite(rho) || !(rho > 0.f)) return EQ_EINVAL;
   return EQ_OK;
@@ -44,7 +46,9 @@ void fill_fwd(FwdArgs &a, const eq_problem *p) {
   a.C = p->C;
   a.n0 = p->n0;
   a.es = p->es;
-  a.rho = p->n0 / p->es;
+  // ZF is the L-MMSE solve with rho = 0; MRC stores G without a shift
+  a.rho = p->equalizer == EQ_LMMSE ? p->n0 / p->es : 0.f;
+  a.eqz = p->equalizer;
   for (int c = 0; c <= p->C; ++c) a.off[c] = (uint16_t)p->cluster_off[c];
   a.spw = fd_spw(ut_for(p->U), p->C);
   a.nsym = 1;
@@ -74,6 +78,10 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   a.fb_done = a.fb_count + 1;
   a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (p->equalizer == EQ_MRC) {
+    const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
+    return launch_mrc(a, fd, prec, s) == hipSuccess ? EQ_OK : EQ_EHIP;
+  }
   if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
   if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
   return EQ_OK;
@@ -90,6 +98,7 @@ eq_status forward_sym(const eq_problem *p, bool fd, int32_t nsym, const eq_c32 *
   if (nsym < 1) return EQ_EINVAL;
   if (nsym > EQ_MAX_SYM) return EQ_ENOTSUP;
   if (p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
+  if (p->equalizer == EQ_MRC) return EQ_ENOTSUP;
   if (p->W == 0) return EQ_OK;
   if (!H || !Y || !Z) return EQ_EINVAL;
   if (!aligned(H, 8) || !aligned(Y, 8) || !aligned(Z, 8)) return EQ_EINVAL;
@@ -133,6 +142,7 @@ eq_status backward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *
                    void *ws, size_t ws_bytes, void *stream) {
   eq_status st = check_problem(p);
   if (st != EQ_OK) return st;
+  if (p->equalizer != EQ_LMMSE) return EQ_ENOTSUP;
   if (!fd && (nu || gnu)) return EQ_EINVAL;
   if (fd && gnu && !nu) return EQ_EINVAL;
   if (p->W == 0) return EQ_OK;
@@ -174,7 +184,7 @@ eq_status backward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *
 extern "C" {
 
 size_t eq_backward_workspace_size(const eq_problem *p) {
-  if (check_problem(p) != EQ_OK) return 0;
+  if (check_problem(p) != EQ_OK || p->equalizer != EQ_LMMSE) return 0;
   return bwd_ws_bytes(p);
 }
 

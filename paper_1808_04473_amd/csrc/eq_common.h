@@ -9,6 +9,9 @@ namespace dbpeq {
 
 enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_BF16X3_NR = 3 };
 
+// Equaliser of the forward calls (the eq_equalizer values).
+enum Eqz { EQZ_LMMSE = 0, EQZ_ZF = 1, EQZ_MRC = 2 };
+
 // Forms that run the refinement step with the FP32 residual y - H z.
 constexpr bool refines(int prec) { return prec == PREC_BF16 || prec == PREC_BF16X3; }
 
@@ -34,6 +37,7 @@ struct FwdArgs {
   // U (z) elements apart
   int32_t nsym;
   int64_t ysw, zsw;
+  int32_t eqz;          // Eqz; ZF runs the L-MMSE kernels with rho = 0
   uint16_t off[EQ_MAX_C + 1];
 };
 
@@ -63,6 +67,8 @@ hipError_t launch_probe_read(const void *buf, size_t bytes, float *sink, hipStre
 // several receive vectors per channel matrix: a.nsym <= symbol_tile(a.U)
 hipError_t launch_symbols(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 int symbol_tile(int U);
+// MRC (no factorisation): FP32 or split-BF16 Gram
+hipError_t launch_mrc(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);

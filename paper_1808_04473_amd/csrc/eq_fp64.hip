@@ -192,7 +192,8 @@ __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
   __shared__ F64Smem sm;
   const int n = min(*a.fb_count, a.W);
   if ((int)blockIdx.x >= n) return;
-  const double rho = (double)a.n0 / (double)a.es;
+  // ZF is the L-MMSE solve with rho = 0
+  const double rho = a.eqz == EQZ_ZF ? 0.0 : (double)a.n0 / (double)a.es;
   const size_t HB = (size_t)a.B * a.U;
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int w = a.fb_list[q];

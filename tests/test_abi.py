@@ -43,13 +43,13 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert lib.eq_abi_version() == 1
+    assert lib.eq_abi_version() == 2
     for st, txt in api.STATUS.items():
         assert lib.eq_status_string(st).decode() == txt
 
 
-def _prob(W=4, B=8, U=2, off=(0, 4, 8), n0=0.1, es=1.0, prec=0):
-    return api.make_problem(W, B, U, list(off), n0, es, prec)
+def _prob(W=4, B=8, U=2, off=(0, 4, 8), n0=0.1, es=1.0, prec=0, eqz=0):
+    return api.make_problem(W, B, U, list(off), n0, es, prec, eqz)
 
 
 # dummy, suitably aligned host addresses: validation must reject before any use
@@ -178,3 +178,34 @@ def test_symbols_validation(lib, fd):
     assert _call_sym(lib, p3, 4, fd) == EINVAL
     p0, _k0 = _prob(W=0)
     assert _call_sym(lib, p0, 4, fd, H=None, Y=None, Z=None, ws=None, wsb=0) == 0
+
+
+def test_problem_struct_layout():
+    # the equaliser field sits in what was the struct's tail padding
+    assert ctypes.sizeof(api.EqProblem) == 40
+    assert api.EqProblem.equalizer.offset == 36
+
+
+@pytest.mark.parametrize("fd", [False, True])
+def test_equalizer_validation(lib, fd):
+    call = _call_fd if fd else _call_pd
+    for bad in (-1, 3, 99):
+        prob, _k = _prob(eqz=bad)
+        assert call(lib, prob) == EINVAL
+        assert lib.eq_workspace_size(ctypes.byref(prob)) == 0
+    # MRC has no refinement step
+    for prec in (1, 2):
+        prob, _k = _prob(eqz=2, prec=prec)
+        assert call(lib, prob) == ENOTSUP
+    # multi-vector calls: L-MMSE and ZF only
+    prob, _k = _prob(eqz=2)
+    assert _call_sym(lib, prob, 4, fd) == ENOTSUP
+    # the adjoint is L-MMSE only
+    for eqz in (1, 2):
+        prob, _k = _prob(eqz=eqz)
+        assert lib.eq_backward_workspace_size(ctypes.byref(prob)) == 0
+        if fd:
+            st = lib.eq_fd_backward(ctypes.byref(prob), A, A, None, A, None, A, A, None, None, A, 1 << 12, None)
+        else:
+            st = lib.eq_pd_backward(ctypes.byref(prob), A, A, A, None, A, A, None, A, 1 << 12, None)
+        assert st == ENOTSUP

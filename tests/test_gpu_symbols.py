@@ -165,3 +165,21 @@ def test_symbols_bench_launch_size():
             ez, es = max_rel_err(host(z[sel]), zr), max_db_err(host(s2[sel]), sr)
             print(f"{mode} {prec} 38400 x 14: {len(idx)} sampled, z err {ez:.2e}, sigma2 {es:.4f} dB", flush=True)
             assert ez <= TOL_Z[prec] and es <= TOL_DB
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_zf_symbols_match_oracle(mode, prec):
+    """equalizer="zf" through the multi-vector calls: each vector against
+    the oracle's ZF on that vector alone."""
+    from paper_1808_04473_amd import api
+    b = synth.make_symbol_batch(30, 256, 16, 8, 14, 10.0, "16qam", seed=41)
+    fn = api.eq_pd_sym if mode == "pd" else api.eq_fd_sym
+    z, s2 = fn(dev(b.H), dev(b.Y), b.n0, b.cluster_off, precision=prec, equalizer="zf")
+    torch.cuda.synchronize()
+    z, s2 = host(z), host(s2)
+    rf = oracle.eq_pd_linear if mode == "pd" else oracle.eq_fd_linear
+    for s in range(b.Y.shape[1]):
+        zr, sr = rf(b.H, b.Y[:, s], b.n0, b.cluster_off, "zf")
+        assert max_rel_err(z[:, s], zr) <= TOL_Z[prec]
+        assert max_db_err(s2, sr) <= TOL_DB
