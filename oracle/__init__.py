@@ -16,6 +16,7 @@ Modules
 lmmse        forward PD / FD L-MMSE (Sections II-C, III-A, IV-A, IV-B), also with
              several receive vectors per channel matrix (Section VI-B)
 linear       PD / FD MRC and ZF (Section III-A, Section IV-A)
+lama         LAMA-PD and LAMA-FD (Algorithm 1; Section IV with the Lemma 2 normalisation)
 adjoint      analytic gradients of both equalisers (derived, not in the paper)
 asymptotics  large-system SINR closed forms (Theorem 1, Corollary 1, Lemma 5)
 
@@ -29,6 +30,8 @@ from .lmmse import (local_statistics, lmmse_estimate, lmmse_error_variance,
                     optimal_fusion_weights, eq_centralized, eq_pd_symbols, eq_fd_symbols)
 from .linear import (mrc_estimate, mrc_error_variance, zf_estimate, zf_error_variance,
                      eq_pd_linear, eq_fd_linear)
+from .lama import (qam_points, posterior_mean_var, lama_pd, lama_original, eq_pd_lama,
+                   eq_fd_lama)
 from .adjoint import pd_backward, fd_backward
 from .asymptotics import (sinr_pd_lmmse, sinr_fd_lmmse, tse_hanly_lmmse_sigma2)
 
@@ -38,6 +41,7 @@ __all__ = [
     "optimal_fusion_weights", "eq_centralized", "eq_pd_symbols", "eq_fd_symbols",
     "mrc_estimate", "mrc_error_variance", "zf_estimate", "zf_error_variance",
     "eq_pd_linear", "eq_fd_linear",
+    "qam_points", "posterior_mean_var", "lama_pd", "lama_original", "eq_pd_lama", "eq_fd_lama",
     "pd_backward", "fd_backward",
     "sinr_pd_lmmse", "sinr_fd_lmmse", "tse_hanly_lmmse_sigma2",
 ]
