@@ -173,9 +173,9 @@ def symbol_measurements(Hn, n0, off, H, steps, S, tag):
 def extra_measurements(Hn, yn, n0, off, H, y, steps):
     """The other rows of the path, each timed the same way and parity-sampled
     against the oracle: single-frame latency (W = 1200), the B = 1024 / U = 32
-    workload in every precision form, ragged batches of 4096 systems, ZF and
-    MRC on the headline systems, 14 receive vectors per channel matrix, and
-    the FD forward + adjoint of the differentiation workload."""
+    workload in every precision form, ragged batches of 4096 systems, ZF,
+    MRC and LAMA on the headline systems, 14 receive vectors per channel
+    matrix, and the FD forward + adjoint of the differentiation workload."""
     import torch
     import oracle
     from paper_1808_04473_amd import api, synth
@@ -260,6 +260,22 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
                           "parity_max_sigma2_db": float(np.max(np.abs(10 * np.log10(s2[sel2].cpu().numpy() / sr))))})
                 t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
                 out[f"{kind}_B256_U16_{mode}_{prec}"] = t
+
+    # LAMA-PD / LAMA-FD (Algorithm 1), 16-QAM, on the headline systems
+    for mode in ("pd", "fd"):
+        fn = api.eq_pd_lama if mode == "pd" else api.eq_fd_lama
+        rf = oracle.eq_pd_lama if mode == "pd" else oracle.eq_fd_lama
+        for t_max in (1, 2, 3):
+            for prec in ("fp32", "bf16x3"):
+                t = _timed(lambda: fn(H, y, n0, off, t_max=t_max, qam=16, precision=prec), steps, 3)
+                z, s2 = fn(H, y, n0, off, t_max=t_max, qam=16, precision=prec)
+                zr, sr = rf(Hn[samp2], yn[samp2], n0, off, t_max, 16)
+                t.update({"subcarriers_per_s": H.shape[0] / (t["call_ms_mean"] * 1e-3),
+                          "alg_GBps": H.shape[0] * bytes_per_system() / (t["call_ms_mean"] * 1e-3) / 1e9,
+                          "parity_max_rel_err_z": _rel_err(z[sel2].cpu().numpy(), zr),
+                          "parity_max_sigma2_db": float(np.max(np.abs(10 * np.log10(s2[sel2].cpu().numpy() / sr))))})
+                t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+                out[f"lama_T{t_max}_B256_U16_{mode}_{prec}"] = t
 
     # several receive vectors per channel matrix: 14 OFDM symbols per subcarrier
     # on the headline channels and on the B = 1024 / U = 32 channels

@@ -50,6 +50,7 @@ extern "C" {
 #define EQ_MAX_B 65535       /* antennas per system */
 #define EQ_MAX_C 1024        /* clusters per system */
 #define EQ_MAX_SYM 1024      /* receive vectors per channel matrix (eq_*_sym) */
+#define EQ_MAX_LAMA_ITER 64  /* LAMA iterations T_max */
 #define EQ_INFO_FP64 (1 << 30)
 #define EQ_COND_LIMIT 1.0e4f
 
@@ -155,6 +156,30 @@ eq_status eq_fd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H,
                     const eq_c32 *Y, const float *nu, eq_c32 *Z, float *sigma2,
                     int32_t *info, void *workspace, size_t workspace_bytes,
                     void *stream);
+
+/* LAMA-PD (Algorithm 1, Section III-C): on the PD statistics (G, y^MRC),
+   starting from s = E[S] = 0, phi = E_s, v = 0, t_max iterations of
+       z = y^MRC + (I - G) s + v,  tau = N0 + beta phi,  beta = U / B,
+       s' = F(z, tau),  phi' = <G(z, tau)>,  v' = beta phi' / tau (z - s),
+   with F, G the posterior mean and variance of eq. (F) for a square QAM of
+   qam_order points (4, 16 or 64) and energy E_s.  Returns z of the last
+   iteration and sigma2 = N0 + beta phi of that iteration (equal for every
+   user of a system).  t_max in 1..EQ_MAX_LAMA_ITER; precision EQ_FP32 or
+   EQ_BF16X3; the equalizer field is not used.  info: 0, or -1 for
+   non-finite statistics (outputs NaN).  No workspace. */
+eq_status eq_pd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order,
+                     const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *sigma2,
+                     int32_t *info, void *stream);
+
+/* LAMA-FD (Section IV): every cluster runs Algorithm 1 on its statistics
+   normalised by 1/sqrt(w_c), w_c = B_c / B (proof of Lemma 2): G_c / w_c,
+   y_c^MRC / w_c, noise N0 / w_c, system ratio beta / w_c; the local
+   estimates are fused as in eq_fd with the variances
+   sigma2_c = N0 / w_c + (beta / w_c) phi_c (or with nu [W][C][U]).
+   info [W][C]. */
+eq_status eq_fd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order,
+                     const eq_c32 *H, const eq_c32 *y, const float *nu, eq_c32 *z,
+                     float *sigma2, int32_t *info, void *stream);
 
 /* Bytes of device workspace the backward calls need. */
 size_t eq_backward_workspace_size(const eq_problem *p);

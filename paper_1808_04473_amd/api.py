@@ -59,6 +59,10 @@ SIGNATURES = [
                             c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_fd_sym", c_int32, [POINTER(EqProblem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_pd_lama", c_int32, [POINTER(EqProblem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p]),
+    ("eq_fd_lama", c_int32, [POINTER(EqProblem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p]),
     ("eq_pd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_fd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -255,6 +259,43 @@ def eq_fd_sym(H, Y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_i
               out=None, ws=None, equalizer="lmmse"):
     """FD L-MMSE (or "zf") of S receive vectors per channel matrix (weights as eq_fd)."""
     return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws, equalizer)
+
+
+def _lama_call(fd, H, y, n0, cluster_off, t_max, qam, nu, precision, es, return_info):
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    C = prob.C
+    if nu is not None:
+        if not fd:
+            raise ValueError("nu applies to FD only")
+        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
+            raise ValueError("nu must be float32 [W][C][U] on the same device")
+        nu = nu.contiguous()
+    z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
+    s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
+    info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
+    if fd:
+        st = lib.eq_fd_lama(ctypes.byref(prob), int(t_max), int(qam), _ptr(H), _ptr(y), _ptr(nu), _ptr(z),
+                            _ptr(s2), _ptr(info), _stream())
+    else:
+        st = lib.eq_pd_lama(ctypes.byref(prob), int(t_max), int(qam), _ptr(H), _ptr(y), _ptr(z), _ptr(s2),
+                            _ptr(info), _stream())
+    _check("eq_fd_lama" if fd else "eq_pd_lama", st)
+    return (z, s2, info) if return_info else (z, s2)
+
+
+def eq_pd_lama(H, y, n0, cluster_off, t_max=2, qam=16, precision="fp32", es=1.0, return_info=False):
+    """LAMA-PD (Algorithm 1) with t_max iterations for square QAM of `qam`
+    points: (z [W][U] c64, sigma2 [W][U] f32)."""
+    return _lama_call(False, H, y, n0, cluster_off, t_max, qam, None, precision, es, return_info)
+
+
+def eq_fd_lama(H, y, n0, cluster_off, t_max=2, qam=16, nu=None, precision="fp32", es=1.0,
+               return_info=False):
+    """LAMA-FD: Algorithm 1 per normalised cluster, fused with Lemma 1's weights (or nu)."""
+    return _lama_call(True, H, y, n0, cluster_off, t_max, qam, nu, precision, es, return_info)
 
 
 def _bwd_workspace(prob: EqProblem, device) -> torch.Tensor:

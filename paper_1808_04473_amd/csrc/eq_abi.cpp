@@ -128,6 +128,35 @@ eq_status forward_sym(const eq_problem *p, bool fd, int32_t nsym, const eq_c32 *
   return EQ_OK;
 }
 
+eq_status forward_lama(const eq_problem *p, bool fd, int32_t t_max, int32_t qam_order, const eq_c32 *H,
+                       const eq_c32 *y, const float *nu, eq_c32 *z, float *s2, int32_t *info, void *stream) {
+  if (!p) return EQ_EINVAL;
+  eq_problem q = *p;
+  q.equalizer = EQ_LMMSE;  // not used by LAMA
+  eq_status st = check_problem(&q);
+  if (st != EQ_OK) return st;
+  if (t_max < 1 || t_max > EQ_MAX_LAMA_ITER) return EQ_EINVAL;
+  if (qam_order != 4 && qam_order != 16 && qam_order != 64) return EQ_EINVAL;
+  if (p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
+  if (p->W == 0) return EQ_OK;
+  if (!H || !y || !z) return EQ_EINVAL;
+  if (!aligned(H, 8) || !aligned(y, 8) || !aligned(z, 8)) return EQ_EINVAL;
+  if ((s2 && !aligned(s2, 4)) || (info && !aligned(info, 4)) || (nu && !aligned(nu, 4))) return EQ_EINVAL;
+  FwdArgs a;
+  fill_fwd(a, &q);
+  a.rho = 0.f;
+  a.H = reinterpret_cast<const float2 *>(H);
+  a.y = reinterpret_cast<const float2 *>(y);
+  a.nu = fd ? nu : nullptr;
+  a.z = reinterpret_cast<float2 *>(z);
+  a.s2 = s2;
+  a.info = info;
+  a.lama_t = t_max;
+  a.lama_m = qam_order == 4 ? 2 : (qam_order == 16 ? 4 : 8);
+  const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
+  return launch_lama(a, fd, prec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? EQ_OK : EQ_EHIP;
+}
+
 size_t bwd_ws_bytes(const eq_problem *p) {
   int spw;
   const int nt = backward_tasks(p->W > 0 ? p->W : 1, p->U, p->C, true, &spw);
@@ -235,6 +264,18 @@ eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z
 eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y, const float *nu, eq_c32 *z,
                 float *sigma2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
   return forward(p, true, H, y, nu, z, sigma2, info, ws, ws_bytes, stream);
+}
+
+eq_status eq_pd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order, const eq_c32 *H, const eq_c32 *y,
+                     eq_c32 *z, float *sigma2, int32_t *info, void *stream) {
+  if (!p) return EQ_EINVAL;
+  return forward_lama(p, false, t_max, qam_order, H, y, nullptr, z, sigma2, info, stream);
+}
+
+eq_status eq_fd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order, const eq_c32 *H, const eq_c32 *y,
+                     const float *nu, eq_c32 *z, float *sigma2, int32_t *info, void *stream) {
+  if (!p) return EQ_EINVAL;
+  return forward_lama(p, true, t_max, qam_order, H, y, nu, z, sigma2, info, stream);
 }
 
 eq_status eq_pd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H, const eq_c32 *Y, eq_c32 *Z,

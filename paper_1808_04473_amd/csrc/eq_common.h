@@ -38,6 +38,8 @@ struct FwdArgs {
   int32_t nsym;
   int64_t ysw, zsw;
   int32_t eqz;          // Eqz; ZF runs the L-MMSE kernels with rho = 0
+  int32_t lama_t;       // LAMA: iterations T_max
+  int32_t lama_m;       // LAMA: levels per coordinate of the square QAM (2, 4, 8)
   uint16_t off[EQ_MAX_C + 1];
 };
 
@@ -69,6 +71,8 @@ hipError_t launch_symbols(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 int symbol_tile(int U);
 // MRC (no factorisation): FP32 or split-BF16 Gram
 hipError_t launch_mrc(const FwdArgs &a, bool fd, int prec, hipStream_t s);
+// LAMA (Algorithm 1): FP32 or split-BF16 Gram
+hipError_t launch_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);

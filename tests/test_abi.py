@@ -209,3 +209,30 @@ def test_equalizer_validation(lib, fd):
         else:
             st = lib.eq_pd_backward(ctypes.byref(prob), A, A, A, None, A, A, None, A, 1 << 12, None)
         assert st == ENOTSUP
+
+
+@pytest.mark.parametrize("fd", [False, True])
+def test_lama_validation(lib, fd):
+    # all rejected (or no-ops) before any HIP call
+    def call(prob, t, q, H=A, y=A, z=A):
+        if fd:
+            return lib.eq_fd_lama(ctypes.byref(prob), t, q, H, y, None, z, A, A, None)
+        return lib.eq_pd_lama(ctypes.byref(prob), t, q, H, y, z, A, A, None)
+    prob, _k = _prob()
+    assert call(prob, 0, 16) == EINVAL
+    assert call(prob, 65, 16) == EINVAL
+    for q in (2, 8, 32, 256):
+        assert call(prob, 2, q) == EINVAL
+    assert call(prob, 2, 16, y=None) == EINVAL
+    assert call(prob, 2, 16, z=A + 4) == EINVAL
+    for prec in (1, 2):
+        p2, _k2 = _prob(prec=prec)
+        assert call(p2, 2, 16) == ENOTSUP
+    p3, _k3 = _prob(n0=-1.0)
+    assert call(p3, 2, 16) == EINVAL
+    p0, _k0 = _prob(W=0)
+    assert call(p0, 2, 16, H=None, y=None, z=None) == 0
+    if fd:
+        assert lib.eq_fd_lama(None, 2, 16, A, A, None, A, A, A, None) == EINVAL
+    else:
+        assert lib.eq_pd_lama(None, 2, 16, A, A, A, A, A, None) == EINVAL
