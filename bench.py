@@ -297,6 +297,18 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
     return out
 
 
+def copy_probe(mib, dev):
+    """One plain device copy of `mib` MiB: the scale reference of the HBM
+    counters (FETCH_SIZE / WRITE_SIZE) in a rocprofv3 --pmc run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def symbols_main(args, dev):
     """--nsym S: the headline channels with S receive vectors each, timed per
     variant the same way (one JSON line; not the headline metric)."""
@@ -304,6 +316,8 @@ def symbols_main(args, dev):
     Hn, _, n0, off = make_inputs(args.frames)
     W = Hn.shape[0]
     H = torch.from_numpy(Hn).to(dev)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib, dev)
     variants = [("pd", "fp32"), ("pd", "bf16x3"), ("fd", "fp32"), ("fd", "bf16x3")] \
         if args.variants == "all" else [tuple(v.split(":")) for v in args.variants.split(",")]
     r = symbol_measurements(Hn, n0, off, H, args.steps, args.nsym, "B256_U16")
@@ -358,12 +372,7 @@ def main(argv=None):
     torch.cuda.synchronize()
 
     if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        copy_probe(args.copy_probe_mib, dev)
 
     variants = VARIANTS if args.variants == "all" else [tuple(v.split(":")) for v in args.variants.split(",")]
     bps = bytes_per_system()
