@@ -92,7 +92,8 @@ typedef enum {
                sigma2_u = N0 / G_uu + E_s sum_{k != u} |G_uk|^2 / G_uu^2
                (the diagonal of the Section III-A MRC variance); no
                factorisation and no FP64 re-solve; EQ_FP32 or EQ_BF16X3 only.
-   The backward calls and the ragged plans are L-MMSE only. */
+   The multi-vector calls take every equaliser; the backward calls and the
+   ragged plans are L-MMSE only. */
 typedef enum { EQ_LMMSE = 0, EQ_ZF = 1, EQ_MRC = 2 } eq_equalizer;
 
 /* Shared description of a batch of W systems. */

@@ -250,14 +250,14 @@ def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws
 
 def eq_pd_sym(H, Y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
               ws=None, equalizer="lmmse"):
-    """PD L-MMSE (or "zf") of S receive vectors per channel matrix: H [W][B][U],
+    """PD L-MMSE (or "zf" / "mrc") of S receive vectors per channel matrix: H [W][B][U],
     Y [W][S][B] -> (Z [W][S][U] c64, sigma2 [W][U] f32).  Precision "fp32" or "bf16x3"."""
     return _sym_call(False, H, Y, n0, cluster_off, None, precision, es, return_info, out, ws, equalizer)
 
 
 def eq_fd_sym(H, Y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
               out=None, ws=None, equalizer="lmmse"):
-    """FD L-MMSE (or "zf") of S receive vectors per channel matrix (weights as eq_fd)."""
+    """FD L-MMSE (or "zf" / "mrc") of S receive vectors per channel matrix (weights as eq_fd)."""
     return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws, equalizer)
 
 

@@ -98,7 +98,6 @@ eq_status forward_sym(const eq_problem *p, bool fd, int32_t nsym, const eq_c32 *
   if (nsym < 1) return EQ_EINVAL;
   if (nsym > EQ_MAX_SYM) return EQ_ENOTSUP;
   if (p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
-  if (p->equalizer == EQ_MRC) return EQ_ENOTSUP;
   if (p->W == 0) return EQ_OK;
   if (!H || !Y || !Z) return EQ_EINVAL;
   if (!aligned(H, 8) || !aligned(Y, 8) || !aligned(Z, 8)) return EQ_EINVAL;

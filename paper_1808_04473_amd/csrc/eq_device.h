@@ -517,8 +517,12 @@ __device__ __forceinline__ float2 &lds_el(float2 (*As)[UT], int i, int k) {
 // Writes G + rho I of one system from the MFMA accumulators into LDS
 // (full Hermitian matrix, swizzled rows):
 //   Re G = Hr^T Hr + Hi^T Hi,   Im G[i][j] = (Hr^T Hi)[i][j] - (Hr^T Hi)[j][i].
+// Rows and columns of padded users (i >= U) are zero; their diagonal gets 1
+// instead of rho, so that the matrix stays positive definite when rho = 0
+// (ZF).  That block is decoupled from the users' block, whose factor and
+// solves it leaves unchanged.
 template <int UT>
-__device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc, float rho) {
+__device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc, float rho, int U = UT) {
   constexpr int NR = UT == 16 ? 4 : 16;
   const int lane = lane_id();
   sfor<NR>([&](auto R) {
@@ -540,7 +544,7 @@ __device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc,
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    lds_el<UT>(As, i, j) = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? rho : 0.f), im[r]);
+    lds_el<UT>(As, i, j) = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? (i < U ? rho : 1.f) : 0.f), im[r]);
   });
 }
 

@@ -341,13 +341,45 @@ __device__ __forceinline__ float2 sym_apply(const SymSolve<UT> &r, SM &sm, int s
   return apply_xh<UT>(r.f, make_float2(tx, ty));
 }
 
+// MRC (Section III-A) on the slot's G (stored unshifted): lane i gets
+// 1 / G_ii and sigma2_i = N0 / G_ii + E_s sum_{k != i} |G_ik|^2 / G_ii^2;
+// fail = u + 1 for the group's first user with G_uu <= 0.
+struct SymMrc {
+  float inv_gii;
+  float s2;
+  int fail;
+  bool bad;
+};
+
+template <int UT, class SM>
+__device__ __forceinline__ SymMrc sym_mrc_row(SM &sm, int slot, int i, int U, float n0, float es) {
+  float gii = 0.f, off = 0.f;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < UT; ++k) {
+    const float2 g = lds_el<UT>(sm.A[slot], i, k);
+    bad |= !finite2(g);
+    if (k == i) gii = g.x;
+    else off = fmaf(g.x, g.x, fmaf(g.y, g.y, off));
+  }
+  SymMrc o;
+  o.bad = gany<UT>(bad);
+  const int base = (lane_id() / UT) * UT;
+  const unsigned long long gm = ((UT == 64 ? ~0ull : ((1ull << UT) - 1ull)) << base);
+  const unsigned long long fm = __ballot(i < U && !(gii > 0.f)) & gm;
+  o.fail = fm ? __builtin_ctzll(fm) - base + 1 : 0;
+  o.inv_gii = 1.0f / gii;
+  o.s2 = n0 * o.inv_gii + es * off * o.inv_gii * o.inv_gii;
+  return o;
+}
+
 __device__ __forceinline__ void enqueue_fp64_sym(const FwdArgs &a, int w) {
   const int pos = atomicAdd(a.fb_count, 1);
   if (pos >= 0 && pos < a.W) a.fb_list[pos] = w;  // capacity W
 }
 
 // PD: systems w0 .. w0+nvalid-1, one per lane group.
-template <int UT, int PREC, class SM>
+template <int UT, int PREC, bool MRC, class SM>
 __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid, SM &sm) {
   const int lane = lane_id();
   const int g = lane / UT, i = lane % UT;
@@ -360,7 +392,7 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
     r1 = a.B;
   };
   gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
-    store_gram<UT>(sm.A[s], acc, a.rho);
+    store_gram<UT>(sm.A[s], acc, a.rho, a.U);
     store_msym<UT, PREC>(sm, s, m);
   });
   for (int s = nvalid; s < SM::NS; ++s) store_identity<UT>(sm.A[s]);
@@ -368,6 +400,21 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
 
   const int slot = slot_of<SM>(g);
   const bool live = g < nvalid;
+  if constexpr (MRC) {
+    const SymMrc o = sym_mrc_row<UT>(sm, slot, i, a.U, a.n0, a.es);
+    const bool out_nan = o.bad || o.fail;
+    const float nanv = __int_as_float(0x7fc00000);
+    const int w = w0 + g;
+    if (live && i < a.U) {
+      float2 *zw = a.z + (size_t)w * a.zsw;
+      for (int s = 0; s < a.nsym; ++s) {
+        const float2 mv = sm.m(slot, s, i);
+        zw[(size_t)s * a.U + i] = out_nan ? make_float2(nanv, nanv) : make_float2(mv.x * o.inv_gii, mv.y * o.inv_gii);
+      }
+      if (a.s2) a.s2[(size_t)w * a.U + i] = out_nan ? nanv : o.s2;
+    }
+    if (live && i == 0 && a.info) a.info[w] = o.bad ? -1 : o.fail;
+  } else {
   SymSolve<UT> r;
   sym_factor<UT>(r, sm, slot, i, a.U);
   const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
@@ -403,15 +450,18 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
       if (routed) enqueue_fp64_sym(a, w);
     }
   }
+  }
 }
 
 // FD: all clusters of subcarrier w, NSYS local systems per round.  The
 // fusion sums (eq. (fusionrule)) run over the clusters in cluster order.
+// MRC (no factor) fuses m_s / G_uu with the 32-lane layout's LDS fusion at
+// every width.
 // 16-lane groups: Z of each cluster comes from MFMA in accumulator layout,
 // and lane (kk, c) keeps the sums of users 4 kk + r of symbol c.  32-lane
 // groups: lane (q, u) = (lane / UT, lane % UT) keeps the sums of user u for
 // the symbols q, q + NSYS, q + 2 NSYS, ...
-template <int UT, int PREC, class SM>
+template <int UT, int PREC, bool MRC, class SM>
 __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
   constexpr int NSYS = 64 / UT;
   constexpr int KS = UT == 16 ? 4 : UT / NSYS;  // sums per lane
@@ -428,6 +478,28 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
 #pragma unroll
   for (int k = 0; k < (UT == 16 ? 4 : 1); ++k) { swk[k] = 0.f; svk[k] = 0.f; }
   bool routed_any = false;
+  // MRC keeps the sums in the (lane / UT, lane % UT) layout at every width
+  constexpr bool mrc = MRC;
+  // fusion of the round's weighted estimates (rows of the slots' matched
+  // filters) and weights (F) by lane (g, i): symbols g, g + NSYS, ...
+  auto valu_fuse = [&](int nvalid) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int s = g + NSYS * k;
+      if (s < a.nsym) {
+        for (int q = 0; q < nvalid; ++q) {
+          const float2 v = sm.m(q, s, i);
+          zf[k].x += v.x;
+          zf[k].y += v.y;
+        }
+      }
+    }
+    for (int q = 0; q < nvalid; ++q) {
+      const float2 v = sm.F[q][i];
+      swk[0] += v.x;
+      svk[0] += v.y;
+    }
+  };
 
   for (int base = 0; base < C; base += NSYS) {
     const int nvalid = min(NSYS, C - base);
@@ -438,7 +510,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       r1 = a.off[base + s + 1];
     };
     gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
-      store_gram<UT>(sm.A[s], acc, a.rho);
+      store_gram<UT>(sm.A[s], acc, a.rho, a.U);
       store_msym<UT, PREC>(sm, s, m);
     });
     for (int s = nvalid; s < NSYS; ++s) store_identity<UT>(sm.A[s]);
@@ -446,6 +518,21 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
 
     const int c = base + g;
     const bool live = g < nvalid;
+    if constexpr (MRC) {
+      const SymMrc o = sym_mrc_row<UT>(sm, g, i, a.U, a.n0, a.es);
+      if (live && i == 0 && a.info) a.info[(size_t)w * C + c] = o.bad ? -1 : o.fail;
+      const bool out_nan = o.bad || o.fail;
+      float p = 0.f;
+      if (live && i < a.U) p = user_nu ? a.nu[((size_t)w * C + c) * a.U + i] : 1.0f / o.s2;
+      const float q = p * o.inv_gii;
+      for (int s = 0; s < a.nsym; ++s) {
+        const float2 mv = sm.m(g, s, i);
+        sm.m(g, s, i) = out_nan ? make_float2(nanv, nanv) : make_float2(q * mv.x, q * mv.y);
+      }
+      sm.F[g][i] = out_nan ? make_float2(nanv, nanv) : make_float2(p, p * p * o.s2);
+      __syncthreads();
+      valu_fuse(nvalid);
+    } else {
     SymSolve<UT> r;
     sym_factor<UT>(r, sm, g, i, a.U);
     const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
@@ -482,28 +569,16 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       }
       sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < KS; ++k) {
-        const int s = g + NSYS * k;
-        if (s < a.nsym) {
-          for (int q = 0; q < nvalid; ++q) {
-            const float2 v = sm.m(q, s, i);
-            zf[k].x += v.x;
-            zf[k].y += v.y;
-          }
-        }
-      }
-      for (int q = 0; q < nvalid; ++q) {
-        const float2 v = sm.F[q][i];
-        swk[0] += v.x;
-        svk[0] += v.y;
-      }
+      valu_fuse(nvalid);
+    }
     }
     __syncthreads();
   }
 
   float2 *zw = a.z + (size_t)w * a.zsw;
-  if constexpr (UT == 16) {
+  bool mfma_layout = false;
+  if constexpr (UT == 16) mfma_layout = !mrc;
+  if (mfma_layout) {
     const int kk = lane >> 4, cs = lane & 15;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -534,14 +609,14 @@ constexpr int sym_pd_per() {
 // One wave per workgroup, one work item per workgroup.  The LDS staging
 // (about 17 KB UT = 16, 17 KB PD / 35 KB FD at UT = 32) bounds occupancy to
 // two waves per SIMD or fewer, which the register target matches.
-template <int UT, int PREC, bool FD>
+template <int UT, int PREC, bool FD, bool MRC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void eq_symbols_kernel(const FwdArgs a) {
   __shared__ SymSmem<UT, FD ? 64 / UT : sym_pd_per<UT>()> sm;
   if constexpr (FD) {
-    fd_sym_task<UT, PREC>(a, blockIdx.x, sm);
+    fd_sym_task<UT, PREC, MRC>(a, blockIdx.x, sm);
   } else {
     const int w0 = blockIdx.x * sym_pd_per<UT>();
-    pd_sym_task<UT, PREC>(a, w0, min(sym_pd_per<UT>(), a.W - w0), sm);
+    pd_sym_task<UT, PREC, MRC>(a, w0, min(sym_pd_per<UT>(), a.W - w0), sm);
   }
 }
 
@@ -549,7 +624,10 @@ template <int UT, int PREC, bool FD>
 static hipError_t launch_sym_one(const FwdArgs &a, hipStream_t s) {
   const int per = FD ? 1 : sym_pd_per<UT>();
   const int grid = (a.W + per - 1) / per;
-  hipLaunchKernelGGL((eq_symbols_kernel<UT, PREC, FD>), dim3(grid), dim3(64), 0, s, a);
+  if (a.eqz == EQZ_MRC)
+    hipLaunchKernelGGL((eq_symbols_kernel<UT, PREC, FD, true>), dim3(grid), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((eq_symbols_kernel<UT, PREC, FD, false>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -197,8 +197,8 @@ def test_equalizer_validation(lib, fd):
     for prec in (1, 2):
         prob, _k = _prob(eqz=2, prec=prec)
         assert call(lib, prob) == ENOTSUP
-    # multi-vector calls: L-MMSE and ZF only
-    prob, _k = _prob(eqz=2)
+    # multi-vector calls take every equaliser, but MRC no refining form
+    prob, _k = _prob(eqz=2, prec=1)
     assert _call_sym(lib, prob, 4, fd) == ENOTSUP
     # the adjoint is L-MMSE only
     for eqz in (1, 2):

@@ -98,6 +98,19 @@ def test_zf_noise_free_recovers_symbols(mode):
     assert np.max(np.abs(z - b.s)) < 1e-4
 
 
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("U", [4, 12, 24])
+def test_zf_padded_users_stay_on_the_fp32_path(mode, U):
+    """Well-conditioned ZF systems with U below the lane-group width (padded
+    users) are solved in FP32: nothing is routed to the FP64 re-solve."""
+    b = synth.make_batch(40, 256, U, 4, 10.0, "16qam", seed=U)
+    z, s2, info = run(mode, "zf", b, "fp32", info=True)
+    assert (info == 0).all(), np.unique(info)
+    zr, sr = ref(mode, "zf", b)
+    assert max_rel_err(z, zr) <= TOL_Z["fp32"]
+    assert max_db_err(s2, sr) <= TOL_DB
+
+
 def test_mrc_user_without_channel():
     """A zero column of H makes G_uu = 0: info = u + 1 and NaN outputs for
     that system only."""

@@ -169,17 +169,40 @@ def test_symbols_bench_launch_size():
 
 @pytest.mark.parametrize("mode", ["pd", "fd"])
 @pytest.mark.parametrize("prec", PRECS)
-def test_zf_symbols_match_oracle(mode, prec):
-    """equalizer="zf" through the multi-vector calls: each vector against
-    the oracle's ZF on that vector alone."""
+@pytest.mark.parametrize("kind", ["zf", "mrc"])
+@pytest.mark.parametrize("shape", [(30, 256, 16, 8, 14), (6, 130, 24, [0, 60, 130], 40), (9, 37, 5, [0, 5, 20, 37], 3)],
+                         ids=lambda s: f"W{s[0]}B{s[1]}U{s[2]}S{s[4]}")
+def test_linear_symbols_match_oracle(mode, prec, kind, shape):
+    """equalizer="zf" / "mrc" through the multi-vector calls: each vector
+    against the oracle's equaliser on that vector alone."""
     from paper_1808_04473_amd import api
-    b = synth.make_symbol_batch(30, 256, 16, 8, 14, 10.0, "16qam", seed=41)
+    W, B, U, C, S = shape
+    off = C if isinstance(C, list) else None
+    nc = len(C) - 1 if isinstance(C, list) else C
+    b = synth.make_symbol_batch(W, B, U, nc, S, 10.0, "16qam", seed=41 + S, cluster_off=off)
     fn = api.eq_pd_sym if mode == "pd" else api.eq_fd_sym
-    z, s2 = fn(dev(b.H), dev(b.Y), b.n0, b.cluster_off, precision=prec, equalizer="zf")
+    z, s2, info = fn(dev(b.H), dev(b.Y), b.n0, b.cluster_off, precision=prec, equalizer=kind, return_info=True)
     torch.cuda.synchronize()
-    z, s2 = host(z), host(s2)
+    z, s2, info = host(z), host(s2), host(info)
+    # ZF on a square local Gram (B_c = U) may be routed to FP64; no failures
+    assert ((info & ~(1 << 30)) == 0).all()
+    if kind == "mrc" or B >= 4 * U:
+        assert (info == 0).all(), np.unique(info)
     rf = oracle.eq_pd_linear if mode == "pd" else oracle.eq_fd_linear
     for s in range(b.Y.shape[1]):
-        zr, sr = rf(b.H, b.Y[:, s], b.n0, b.cluster_off, "zf")
+        zr, sr = rf(b.H, b.Y[:, s], b.n0, b.cluster_off, kind)
         assert max_rel_err(z[:, s], zr) <= TOL_Z[prec]
         assert max_db_err(s2, sr) <= TOL_DB
+
+
+def test_mrc_symbols_user_without_channel():
+    """MRC through the multi-vector call: a zero column of H gives info =
+    u + 1 and NaN for every vector of that subcarrier only."""
+    from paper_1808_04473_amd import api
+    b = synth.make_symbol_batch(5, 64, 8, 2, 6, 10.0, "qpsk", seed=43)
+    b.H[2, :, 4] = 0
+    z, s2, info = api.eq_pd_sym(dev(b.H), dev(b.Y), b.n0, b.cluster_off, equalizer="mrc", return_info=True)
+    torch.cuda.synchronize()
+    z, info = host(z), host(info)
+    assert info[2] == 5 and np.isnan(z[2]).all()
+    assert (info[np.arange(5) != 2] == 0).all() and np.isfinite(z[np.arange(5) != 2]).all()
