@@ -185,7 +185,7 @@ __device__ __forceinline__ void gram_round(const BwdArgs &a, BSmem<UT> &sm, int 
   constexpr int NSYS = 64 / UT;
   const int lane = lane_id();
   gram_stream<UT, PREC_FP32, kLoadKeep>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-    store_gram<UT>(sm.r.A[s], acc, a.rho);
+    store_gram<UT, PREC_FP32>(sm.r.A[s], acc, a.rho);
     if (lane < UT) sm.r.M[s][lane] = mf;
   });
   for (int s = nvalid; s < NSYS; ++s) {

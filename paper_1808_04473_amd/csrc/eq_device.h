@@ -401,8 +401,11 @@ __device__ __forceinline__ void stream_blocks(int ns, int U, Seg seg, Body body,
 }
 
 // ---------------------------------------------------------------- Gram + matched filter
-// acc += real split of the block's H^H H (rr = Hr^T Hr, ri = Hr^T Hi,
-// ii = Hi^T Hi); (mfx, mfy) += partial of sum conj(H[row][col]) y[row].
+// acc += real split of the block's H^H H: rr = Hr^T Hr, ri = Hr^T Hi,
+// ii = Hi^T Hi in the BF16 forms; in FP32, two products only, rr = P =
+// (Hr + Hi)^T (Hr + Hi) = Hr^T Hr + Hi^T Hi + ri + ri^T and ri (Re G needs
+// only the sum of the two squares, store_gram takes ri + ri^T back out).
+// (mfx, mfy) += partial of sum conj(H[row][col]) y[row].
 template <int UT, int PREC>
 __device__ __forceinline__ void gram_blk(const Slot &sl, int U, Acc<UT> &acc, float &mfx, float &mfy) {
   Blk8 b;
@@ -411,9 +414,9 @@ __device__ __forceinline__ void gram_blk(const Slot &sl, int U, Acc<UT> &acc, fl
   if constexpr (PREC == PREC_FP32) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      acc.rr = mma32(b.h[e].x, b.h[e].x, acc.rr);
+      const float sum = b.h[e].x + b.h[e].y;
+      acc.rr = mma32(sum, sum, acc.rr);
       acc.ri = mma32(b.h[e].x, b.h[e].y, acc.ri);
-      acc.ii = mma32(b.h[e].y, b.h[e].y, acc.ii);
     }
   } else if constexpr (PREC == PREC_BF16) {
     bf8 re, im;
@@ -516,12 +519,13 @@ __device__ __forceinline__ float2 &lds_el(float2 (*As)[UT], int i, int k) {
 
 // Writes G + rho I of one system from the MFMA accumulators into LDS
 // (full Hermitian matrix, swizzled rows):
-//   Re G = Hr^T Hr + Hi^T Hi,   Im G[i][j] = (Hr^T Hi)[i][j] - (Hr^T Hi)[j][i].
+//   Re G = Hr^T Hr + Hi^T Hi,   Im G[i][j] = (Hr^T Hi)[i][j] - (Hr^T Hi)[j][i],
+// with Re G = P - ri - ri^T for the FP32 accumulators (see gram_blk).
 // Rows and columns of padded users (i >= U) are zero; their diagonal gets 1
 // instead of rho, so that the matrix stays positive definite when rho = 0
 // (ZF).  That block is decoupled from the users' block, whose factor and
 // solves it leaves unchanged.
-template <int UT>
+template <int UT, int PREC>
 __device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc, float rho, int U = UT) {
   constexpr int NR = UT == 16 ? 4 : 16;
   const int lane = lane_id();
@@ -532,19 +536,21 @@ __device__ __forceinline__ void store_gram(float2 (*As)[UT], const Acc<UT> &acc,
     lds_el<UT>(As, i, j) = make_float2(0.f, acc.ri[r]);
   });
   __syncthreads();
-  float im[NR];
+  float im[NR], re[NR];
   sfor<NR>([&](auto R) {
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    im[r] = acc.ri[r] - lds_el<UT>(As, j, i).y;
+    const float rij = lds_el<UT>(As, j, i).y;  // (Hr^T Hi)[j][i]
+    im[r] = acc.ri[r] - rij;
+    re[r] = PREC == PREC_FP32 ? acc.rr[r] - acc.ri[r] - rij : acc.rr[r] + acc.ii[r];
   });
   __syncthreads();
   sfor<NR>([&](auto R) {
     constexpr int r = R;
     int i, j;
     acc_pos<UT>(lane, r, i, j);
-    lds_el<UT>(As, i, j) = make_float2(acc.rr[r] + acc.ii[r] + (i == j ? (i < U ? rho : 1.f) : 0.f), im[r]);
+    lds_el<UT>(As, i, j) = make_float2(re[r] + (i == j ? (i < U ? rho : 1.f) : 0.f), im[r]);
   });
 }
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, SM
   // ---- Gram + matched filter of the round's subcarriers (all clusters
   //      accumulate into one G and one y^MRC: the adder tree of eq. (fullMRC))
   gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-    store_gram<UT>(sm.A[s], acc, a.rho, a.U);
+    store_gram<UT, PREC>(sm.A[s], acc, a.rho, a.U);
     if (lane < UT) sm.M[s][lane] = mf;
   });
   for (int s = nvalid; s < SM::NS; ++s) {
@@ -131,7 +131,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, SM &
     };
     // ---- local Gram + MRC of the clusters of this round
     gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-      store_gram<UT>(sm.A[s], acc, a.rho, a.U);
+      store_gram<UT, PREC>(sm.A[s], acc, a.rho, a.U);
       if (lane < UT) sm.M[s][lane] = mf;
     });
     for (int s = nvalid; s < NSYS; ++s) {

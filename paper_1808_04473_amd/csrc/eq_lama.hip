@@ -105,7 +105,7 @@ __device__ __forceinline__ void lama_pd_task(const FwdArgs &a, int w0, int nvali
     r1 = a.B;
   };
   gram_stream<UT, PREC, kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-    store_gram<UT>(sm.A[s], acc, 0.f);
+    store_gram<UT, PREC>(sm.A[s], acc, 0.f);
     if (lane < UT) sm.M[s][lane] = mf;
   });
   for (int s = nvalid; s < 64 / UT; ++s) {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void lama_fd_task(const FwdArgs &a, int w, Smem<UT> &
       r1 = a.off[base + s + 1];
     };
     gram_stream<UT, PREC, kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-      store_gram<UT>(sm.A[s], acc, 0.f);
+      store_gram<UT, PREC>(sm.A[s], acc, 0.f);
       if (lane < UT) sm.M[s][lane] = mf;
     });
     for (int s = nvalid; s < NSYS; ++s) {

@@ -60,7 +60,7 @@ __device__ __forceinline__ void mrc_pd_task(const FwdArgs &a, int w0, int nvalid
     r1 = a.B;
   };
   gram_stream<UT, PREC, kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-    store_gram<UT>(sm.A[s], acc, 0.f);
+    store_gram<UT, PREC>(sm.A[s], acc, 0.f);
     if (lane < UT) sm.M[s][lane] = mf;
   });
   __syncthreads();
@@ -95,7 +95,7 @@ __device__ __forceinline__ void mrc_fd_task(const FwdArgs &a, int w, Smem<UT> &s
       r1 = a.off[base + s + 1];
     };
     gram_stream<UT, PREC, kLoadLast>(nvalid, a.U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-      store_gram<UT>(sm.A[s], acc, 0.f);
+      store_gram<UT, PREC>(sm.A[s], acc, 0.f);
       if (lane < UT) sm.M[s][lane] = mf;
     });
     __syncthreads();

@@ -25,7 +25,7 @@ __device__ __forceinline__ void ragged_pd(const RaggedArgs &a, const RTask &task
     r1 = d.B;
   };
   gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-    store_gram<UT>(sm.A[s], acc, a.sys[sysk(s)].rho);
+    store_gram<UT, PREC>(sm.A[s], acc, a.sys[sysk(s)].rho);
     if (lane < UT) sm.M[s][lane] = mf;
   });
   for (int s = n; s < NSYS; ++s) {
@@ -79,7 +79,7 @@ __device__ __forceinline__ void ragged_fd(const RaggedArgs &a, const RTask &task
       r1 = a.offs[d.off_first + base + s + 1];
     };
     gram_stream<UT, PREC, refines(PREC) ? kLoadKeep : kLoadLast>(n, U, seg, [&](int s, const Acc<UT> &acc, float2 mf) {
-      store_gram<UT>(sm.A[s], acc, d.rho);
+      store_gram<UT, PREC>(sm.A[s], acc, d.rho);
       if (lane < UT) sm.M[s][lane] = mf;
     });
     for (int s = n; s < NSYS; ++s) {

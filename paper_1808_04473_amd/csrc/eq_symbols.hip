@@ -106,7 +106,8 @@ __device__ __forceinline__ float2 macc_value(const MAcc<UT> &m, int r) {
   else return make_float2(m.k1[r], m.k2[r]);
 }
 
-// acc += real split of the block's H^H H; m += H^H Y of the block.
+// acc += the block's Gram products (as gram_blk: P and ri in FP32, the
+// split products otherwise); m += H^H Y of the block.
 template <int UT, int PREC>
 __device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAcc<UT> &m) {
   float2 y[8];
@@ -116,11 +117,11 @@ __device__ __forceinline__ void gram_mf_blk(const SymSlot &sl, Acc<UT> &acc, MAc
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float2 h = sl.h[e];
-      acc.rr = mma32(h.x, h.x, acc.rr);
+      const float sum = h.x + h.y;
+      acc.rr = mma32(sum, sum, acc.rr);
       m.k1 = mma32(h.x - h.y, y[e].x, m.k1);
       acc.ri = mma32(h.x, h.y, acc.ri);
       m.k2 = mma32(h.x, y[e].y - y[e].x, m.k2);
-      acc.ii = mma32(h.y, h.y, acc.ii);
       m.k3 = mma32(h.y, y[e].x + y[e].y, m.k3);
     }
   } else {
@@ -392,7 +393,7 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
     r1 = a.B;
   };
   gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
-    store_gram<UT>(sm.A[s], acc, a.rho, a.U);
+    store_gram<UT, PREC>(sm.A[s], acc, a.rho, a.U);
     store_msym<UT, PREC>(sm, s, m);
   });
   for (int s = nvalid; s < SM::NS; ++s) store_identity<UT>(sm.A[s]);
@@ -510,7 +511,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       r1 = a.off[base + s + 1];
     };
     gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
-      store_gram<UT>(sm.A[s], acc, a.rho, a.U);
+      store_gram<UT, PREC>(sm.A[s], acc, a.rho, a.U);
       store_msym<UT, PREC>(sm, s, m);
     });
     for (int s = nvalid; s < NSYS; ++s) store_identity<UT>(sm.A[s]);
