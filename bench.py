@@ -97,20 +97,36 @@ VARIANTS = [("pd", "fp32"), ("pd", "bf16x3"), ("pd", "bf16_refine"), ("pd", "bf1
             ("fd", "fp32"), ("fd", "bf16x3"), ("fd", "bf16_refine"), ("fd", "bf16x3_refine")]
 
 
-def _timed(fn, steps, warmup):
-    """Median / p10 / p90 of per-call HIP-event times (ms) on the current stream."""
+def _per_call(fn, steps):
+    """Per-call HIP-event times (ms) of `steps` calls, each bracketed by its
+    own event pair (the pairs add a gap of their own between calls, so these
+    describe the spread, not the throughput)."""
     import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for e0, e1 in ev:
         e0.record()
         fn()
         e1.record()
     torch.cuda.synchronize()
-    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
-    return {"call_ms_median": float(np.median(per)), "call_ms_mean": float(np.mean(per)),
+    return np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+
+
+def _timed(fn, steps, warmup):
+    """Mean time per call (ms) of `steps` back-to-back calls between one pair
+    of HIP events on the current stream, plus median / p10 / p90 of calls
+    timed one by one."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    per = _per_call(fn, steps)
+    return {"call_ms_mean": e0.elapsed_time(e1) / steps, "call_ms_median": float(np.median(per)),
             "call_ms_p10": float(np.percentile(per, 10)), "call_ms_p90": float(np.percentile(per, 90))}
 
 
@@ -393,21 +409,23 @@ def main(argv=None):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+        # the timed region: K back-to-back steps between one pair of HIP events
+        # on the library's stream, synchronised on both sides
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        for e0, e1 in ev:
-            e0.record()
+        e0.record()
+        for _ in range(args.steps):
             step()
-            e1.record()
+        e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms, per call on the stream
+        call_ms = e0.elapsed_time(e1) / args.steps
+        per = _per_call(step, min(args.steps, 20))  # spread of single calls
         ms = wall * 1e3 / args.steps
-        r = {"ms_per_step": ms, "subcarriers_per_s": W / (ms * 1e-3),
-             "call_ms_median": float(np.median(per)), "call_ms_p10": float(np.percentile(per, 10)),
-             "call_ms_p90": float(np.percentile(per, 90)),
-             "alg_GBps": W * bps / (float(np.mean(per)) * 1e-3) / 1e9}
+        r = {"ms_per_step": ms, "subcarriers_per_s": W / (ms * 1e-3), "call_ms_mean": call_ms,
+             "call_ms_median_single": float(np.median(per)), "call_ms_p10_single": float(np.percentile(per, 10)),
+             "call_ms_p90_single": float(np.percentile(per, 90)),
+             "alg_GBps": W * bps / (call_ms * 1e-3) / 1e9}
         r["hbm_frac"] = r["alg_GBps"] / HBM_PEAK_GBS
         r["fp64_routed"] = int(((info & (1 << 30)) != 0).any(dim=-1).sum().item()) if mode == "fd" \
             else int(((info & (1 << 30)) != 0).sum().item())
