@@ -164,6 +164,25 @@ def symbol_measurements(Hn, n0, off, H, steps, S, tag):
     sel = torch.from_numpy(samp).to(dev)
     nb = W * bytes_per_system_sym(Bs, Us, S)
     out = {}
+    # LAMA (T_max = 2, 16-QAM) over the same vectors, against 14 single-vector LAMA calls
+    for mode in ("pd", "fd"):
+        fs = api.eq_pd_lama_sym if mode == "pd" else api.eq_fd_lama_sym
+        f1 = api.eq_pd_lama if mode == "pd" else api.eq_fd_lama
+        rf = oracle.eq_pd_lama if mode == "pd" else oracle.eq_fd_lama
+        t = _timed(lambda: fs(Hd, Y, n0, off, t_max=2, qam=16), steps, 3)
+        t1 = _timed(lambda: f1(Hd, y1, n0, off, t_max=2, qam=16), steps, 3)
+        z, s2 = fs(Hd, Y, n0, off, t_max=2, qam=16)
+        zs = z[sel].cpu().numpy()
+        errs = [_rel_err(zs[:, s], rf(Hn[samp], Yn[samp, s], n0, off, 2, 16)[0]) for s in range(0, S, 5)]
+        t.update({"subcarriers_per_s": W / (t["call_ms_mean"] * 1e-3),
+                  "vectors_per_s": W * S / (t["call_ms_mean"] * 1e-3),
+                  "alg_GBps": (nb + W * S * Us * 4) / (t["call_ms_mean"] * 1e-3) / 1e9,
+                  "single_vector_call_ms_mean": t1["call_ms_mean"],
+                  "speedup_vs_single_vector_calls": S * t1["call_ms_mean"] / t["call_ms_mean"],
+                  "parity_max_rel_err_z": float(max(errs))})
+        t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+        out[f"symbols{S}_{tag}_{mode}_lama_T2_fp32"] = t
+        del z, s2
     for mode in ("pd", "fd"):
         fs = api.eq_pd_sym if mode == "pd" else api.eq_fd_sym
         f1 = api.eq_pd if mode == "pd" else api.eq_fd

@@ -182,6 +182,20 @@ eq_status eq_fd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order,
                      const eq_c32 *H, const eq_c32 *y, const float *nu, eq_c32 *z,
                      float *sigma2, int32_t *info, void *stream);
 
+/* LAMA-PD / LAMA-FD over several receive vectors per channel matrix
+   (Section VI-B runs LAMA over N_sc x N_sym vectors with the Gram formed once
+   per subcarrier): Y [W][nsym][B], Z [W][nsym][U] as for eq_pd_sym, and
+   sigma2 [W][nsym][U], since LAMA's variance N0 + beta phi depends on the
+   vector.  Each vector gets what eq_pd_lama / eq_fd_lama give for it alone;
+   arguments and info as there. */
+eq_status eq_pd_lama_sym(const eq_problem *p, int32_t nsym, int32_t t_max,
+                         int32_t qam_order, const eq_c32 *H, const eq_c32 *Y,
+                         eq_c32 *Z, float *sigma2, int32_t *info, void *stream);
+eq_status eq_fd_lama_sym(const eq_problem *p, int32_t nsym, int32_t t_max,
+                         int32_t qam_order, const eq_c32 *H, const eq_c32 *Y,
+                         const float *nu, eq_c32 *Z, float *sigma2,
+                         int32_t *info, void *stream);
+
 /* Bytes of device workspace the backward calls need. */
 size_t eq_backward_workspace_size(const eq_problem *p);
 

@@ -63,6 +63,10 @@ SIGNATURES = [
                              c_void_p, c_void_p, c_void_p]),
     ("eq_fd_lama", c_int32, [POINTER(EqProblem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("eq_pd_lama_sym", c_int32, [POINTER(EqProblem), c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("eq_fd_lama_sym", c_int32, [POINTER(EqProblem), c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("eq_pd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_fd_backward", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -296,6 +300,43 @@ def eq_fd_lama(H, y, n0, cluster_off, t_max=2, qam=16, nu=None, precision="fp32"
                return_info=False):
     """LAMA-FD: Algorithm 1 per normalised cluster, fused with Lemma 1's weights (or nu)."""
     return _lama_call(True, H, y, n0, cluster_off, t_max, qam, nu, precision, es, return_info)
+
+
+def _lama_sym_call(fd, H, Y, n0, cluster_off, t_max, qam, nu, precision, es, return_info):
+    lib = load_library()
+    H, Y = _check_sym_inputs(H, Y)
+    W, B, U = H.shape
+    S = Y.shape[1]
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
+    C = prob.C
+    if nu is not None:
+        if not fd:
+            raise ValueError("nu applies to FD only")
+        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
+            raise ValueError("nu must be float32 [W][C][U] on the same device")
+        nu = nu.contiguous()
+    z = torch.empty((W, S, U), dtype=torch.complex64, device=H.device)
+    s2 = torch.empty((W, S, U), dtype=torch.float32, device=H.device)
+    info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
+    if fd:
+        st = lib.eq_fd_lama_sym(ctypes.byref(prob), S, int(t_max), int(qam), _ptr(H), _ptr(Y), _ptr(nu),
+                                _ptr(z), _ptr(s2), _ptr(info), _stream())
+    else:
+        st = lib.eq_pd_lama_sym(ctypes.byref(prob), S, int(t_max), int(qam), _ptr(H), _ptr(Y), _ptr(z),
+                                _ptr(s2), _ptr(info), _stream())
+    _check("eq_fd_lama_sym" if fd else "eq_pd_lama_sym", st)
+    return (z, s2, info) if return_info else (z, s2)
+
+
+def eq_pd_lama_sym(H, Y, n0, cluster_off, t_max=2, qam=16, precision="fp32", es=1.0, return_info=False):
+    """LAMA-PD of S receive vectors per channel matrix: (Z [W][S][U], sigma2 [W][S][U])."""
+    return _lama_sym_call(False, H, Y, n0, cluster_off, t_max, qam, None, precision, es, return_info)
+
+
+def eq_fd_lama_sym(H, Y, n0, cluster_off, t_max=2, qam=16, nu=None, precision="fp32", es=1.0,
+                   return_info=False):
+    """LAMA-FD of S receive vectors per channel matrix (weights as eq_fd_lama)."""
+    return _lama_sym_call(True, H, Y, n0, cluster_off, t_max, qam, nu, precision, es, return_info)
 
 
 def _bwd_workspace(prob: EqProblem, device) -> torch.Tensor:

@@ -156,6 +156,48 @@ eq_status forward_lama(const eq_problem *p, bool fd, int32_t t_max, int32_t qam_
   return launch_lama(a, fd, prec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? EQ_OK : EQ_EHIP;
 }
 
+// LAMA over several receive vectors: Y [W][nsym][B], Z and sigma2
+// [W][nsym][U]; tiles of up to symbol_tile(U) vectors, each reading H once.
+eq_status forward_lama_sym(const eq_problem *p, bool fd, int32_t nsym, int32_t t_max, int32_t qam_order,
+                           const eq_c32 *H, const eq_c32 *Y, const float *nu, eq_c32 *Z, float *s2, int32_t *info,
+                           void *stream) {
+  if (!p) return EQ_EINVAL;
+  eq_problem q = *p;
+  q.equalizer = EQ_LMMSE;  // not used by LAMA
+  eq_status st = check_problem(&q);
+  if (st != EQ_OK) return st;
+  if (nsym < 1) return EQ_EINVAL;
+  if (nsym > EQ_MAX_SYM) return EQ_ENOTSUP;
+  if (t_max < 1 || t_max > EQ_MAX_LAMA_ITER) return EQ_EINVAL;
+  if (qam_order != 4 && qam_order != 16 && qam_order != 64) return EQ_EINVAL;
+  if (p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
+  if (p->W == 0) return EQ_OK;
+  if (!H || !Y || !Z) return EQ_EINVAL;
+  if (!aligned(H, 8) || !aligned(Y, 8) || !aligned(Z, 8)) return EQ_EINVAL;
+  if ((s2 && !aligned(s2, 4)) || (info && !aligned(info, 4)) || (nu && !aligned(nu, 4))) return EQ_EINVAL;
+  FwdArgs a;
+  fill_fwd(a, &q);
+  a.rho = 0.f;
+  a.H = reinterpret_cast<const float2 *>(H);
+  a.nu = fd ? nu : nullptr;
+  a.info = info;
+  a.lama_t = t_max;
+  a.lama_m = qam_order == 4 ? 2 : (qam_order == 16 ? 4 : 8);
+  a.ysw = (int64_t)nsym * p->B;
+  a.zsw = (int64_t)nsym * p->U;
+  const int tile = symbol_tile(p->U);
+  const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int s0 = 0; s0 < nsym; s0 += tile) {
+    a.nsym = nsym - s0 < tile ? nsym - s0 : tile;
+    a.y = reinterpret_cast<const float2 *>(Y) + (size_t)s0 * p->B;
+    a.z = reinterpret_cast<float2 *>(Z) + (size_t)s0 * p->U;
+    a.s2 = s2 ? s2 + (size_t)s0 * p->U : nullptr;
+    if (launch_symbols_lama(a, fd, prec, s) != hipSuccess) return EQ_EHIP;
+  }
+  return EQ_OK;
+}
+
 size_t bwd_ws_bytes(const eq_problem *p) {
   int spw;
   const int nt = backward_tasks(p->W > 0 ? p->W : 1, p->U, p->C, true, &spw);
@@ -275,6 +317,17 @@ eq_status eq_fd_lama(const eq_problem *p, int32_t t_max, int32_t qam_order, cons
                      const float *nu, eq_c32 *z, float *sigma2, int32_t *info, void *stream) {
   if (!p) return EQ_EINVAL;
   return forward_lama(p, true, t_max, qam_order, H, y, nu, z, sigma2, info, stream);
+}
+
+eq_status eq_pd_lama_sym(const eq_problem *p, int32_t nsym, int32_t t_max, int32_t qam_order, const eq_c32 *H,
+                         const eq_c32 *Y, eq_c32 *Z, float *sigma2, int32_t *info, void *stream) {
+  return forward_lama_sym(p, false, nsym, t_max, qam_order, H, Y, nullptr, Z, sigma2, info, stream);
+}
+
+eq_status eq_fd_lama_sym(const eq_problem *p, int32_t nsym, int32_t t_max, int32_t qam_order, const eq_c32 *H,
+                         const eq_c32 *Y, const float *nu, eq_c32 *Z, float *sigma2, int32_t *info,
+                         void *stream) {
+  return forward_lama_sym(p, true, nsym, t_max, qam_order, H, Y, nu, Z, sigma2, info, stream);
 }
 
 eq_status eq_pd_sym(const eq_problem *p, int32_t nsym, const eq_c32 *H, const eq_c32 *Y, eq_c32 *Z,

@@ -71,8 +71,10 @@ hipError_t launch_symbols(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 int symbol_tile(int U);
 // MRC (no factorisation): FP32 or split-BF16 Gram
 hipError_t launch_mrc(const FwdArgs &a, bool fd, int prec, hipStream_t s);
-// LAMA (Algorithm 1): FP32 or split-BF16 Gram
+// LAMA (Algorithm 1): FP32 or split-BF16 Gram; one receive vector, or a tile
+// of a.nsym <= symbol_tile(a.U) vectors per channel matrix
 hipError_t launch_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s);
+hipError_t launch_symbols_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);

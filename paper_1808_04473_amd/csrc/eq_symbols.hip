@@ -17,11 +17,14 @@
 // estimates with the weights of Lemma 1 (or given ones), which do not depend
 // on the symbol, and sums them over the clusters in cluster order.
 //
+// LAMA (Algorithm 1) runs on the same pass, the iteration once per vector
+// with the system's Gram row held in registers (eq_symbols_lama_kernel).
+//
 // Forms: FP32 MFMA (the matched filter as three real products), and
 // split-BF16 MFMA (three products per real product) without refinement; the refining forms are not offered for several
 // symbols.  Ill-conditioned systems go to the FP64 re-solve queue as in the
 // single-vector kernels; the re-solve recomputes every symbol of the tile.
-#include "eq_round.h"
+#include "eq_lama.h"
 
 namespace dbpeq {
 
@@ -601,6 +604,149 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
   if (lane == 0 && routed_any) enqueue_fp64_sym(a, w);
 }
 
+// ---------------------------------------------------------------- LAMA
+// LAMA (Algorithm 1) for every receive vector of the tile: one Gram per
+// subcarrier (PD) or cluster (FD), the iteration per vector.  LAMA's
+// variance N0 + beta phi depends on the vector, so sigma2 is [W][S][U] here.
+
+// Lane i of group g: f.x = conj(row i of the slot's G) * scale.
+template <int UT, class SM>
+__device__ __forceinline__ bool lama_load_row(Factor<UT> &f, SM &sm, int slot, int i, float scale) {
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < UT; ++k) {
+    const float2 g = lds_el<UT>(sm.A[slot], i, k);
+    bad |= !finite2(g);
+    f.x[k] = make_float2(g.x * scale, -g.y * scale);
+  }
+  return gany<UT>(bad);
+}
+
+template <int UT, int PREC, int M, class SM>
+__device__ __forceinline__ void pd_sym_lama_task(const FwdArgs &a, int w0, int nvalid, SM &sm) {
+  const int lane = lane_id();
+  const int g = lane / UT, i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+  auto seg = [&](int s, const float2 *&Hw, const float2 *&Yw, int &r0, int &r1) {
+    const size_t w = (size_t)w0 + s;
+    Hw = a.H + w * HB;
+    Yw = a.y + w * (size_t)a.ysw;
+    r0 = 0;
+    r1 = a.B;
+  };
+  gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
+    store_gram<UT, PREC>(sm.A[s], acc, 0.f, a.U);
+    store_msym<UT, PREC>(sm, s, m);
+  });
+  for (int s = nvalid; s < SM::NS; ++s) store_identity<UT>(sm.A[s]);
+  __syncthreads();
+  const int slot = slot_of<SM>(g);
+  const bool live = g < nvalid;
+  const int w = w0 + g;
+  Factor<UT> f;
+  const bool bad = lama_load_row<UT>(f, sm, slot, i, 1.0f);
+  const float beta = (float)a.U / (float)a.B;
+  const float nanv = __int_as_float(0x7fc00000);
+  const size_t ob = (size_t)w * a.zsw;
+  for (int s = 0; s < a.nsym; ++s) {
+    float2 z;
+    float tau;
+    lama_iterate<UT, M>(f, sm.m(slot, s, i), i, a.U, a.n0, beta, a.es, a.lama_t, z, tau);
+    if (live && i < a.U) {
+      a.z[ob + (size_t)s * a.U + i] = bad ? make_float2(nanv, nanv) : z;
+      if (a.s2) a.s2[ob + (size_t)s * a.U + i] = bad ? nanv : tau;
+    }
+  }
+  if (live && i == 0 && a.info) a.info[w] = bad ? -1 : 0;
+}
+
+// FD: rounds of NSYS clusters.  After a cluster's iteration for vector s,
+// lane (g, i) leaves nu z in the slot's matched-filter row s and (nu,
+// nu^2 sigma2_c) in row s of the slot's (no longer needed) G; fusion lane
+// (g, i) then sums user i of the vectors g, g + NSYS, ... over the clusters.
+template <int UT, int PREC, int M, class SM>
+__device__ __forceinline__ void fd_sym_lama_task(const FwdArgs &a, int w, SM &sm) {
+  constexpr int NSYS = 64 / UT;
+  constexpr int KS = UT / NSYS;
+  const int lane = lane_id();
+  const int g = lane / UT, i = lane % UT;
+  const size_t HB = (size_t)a.B * a.U;
+  const int C = a.C;
+  const bool user_nu = a.nu != nullptr;
+  const float nanv = __int_as_float(0x7fc00000);
+  const float beta = (float)a.U / (float)a.B;
+  float2 zf[KS];
+  float swk[KS], svk[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    zf[k] = make_float2(0.f, 0.f);
+    swk[k] = 0.f;
+    svk[k] = 0.f;
+  }
+  for (int base = 0; base < C; base += NSYS) {
+    const int nvalid = min(NSYS, C - base);
+    auto seg = [&](int s, const float2 *&Hw, const float2 *&Yw, int &r0, int &r1) {
+      Hw = a.H + (size_t)w * HB;
+      Yw = a.y + (size_t)w * a.ysw;
+      r0 = a.off[base + s];
+      r1 = a.off[base + s + 1];
+    };
+    gram_mf_stream<UT, PREC>(nvalid, a.U, a.B, a.nsym, seg, [&](int s, const Acc<UT> &acc, const MAcc<UT> &m) {
+      store_gram<UT, PREC>(sm.A[s], acc, 0.f, a.U);
+      store_msym<UT, PREC>(sm, s, m);
+    });
+    for (int s = nvalid; s < NSYS; ++s) store_identity<UT>(sm.A[s]);
+    __syncthreads();
+    const int c = base + g;
+    const bool live = g < nvalid;
+    const float wc = live ? (float)(a.off[c + 1] - a.off[c]) / (float)a.B : 1.0f;
+    const float iw = 1.0f / wc;
+    Factor<UT> f;
+    const bool bad = lama_load_row<UT>(f, sm, g, i, iw);
+    if (live && i == 0 && a.info) a.info[(size_t)w * C + c] = bad ? -1 : 0;
+    float nu = 0.f;
+    if (user_nu && live && i < a.U) nu = a.nu[((size_t)w * C + c) * a.U + i];
+    __syncthreads();  // every row of G is in registers: the slots' G rows are free
+    for (int s = 0; s < a.nsym; ++s) {
+      const float2 mv = sm.m(g, s, i);
+      float2 z;
+      float tau;
+      lama_iterate<UT, M>(f, make_float2(mv.x * iw, mv.y * iw), i, a.U, a.n0 * iw, beta * iw, a.es, a.lama_t, z, tau);
+      const float p = (live && i < a.U) ? (user_nu ? nu : 1.0f / tau) : 0.f;
+      sm.m(g, s, i) = bad ? make_float2(nanv, nanv) : make_float2(p * z.x, p * z.y);
+      lds_el<UT>(sm.A[g], s, i) = bad ? make_float2(nanv, nanv) : make_float2(p, p * p * tau);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int s = g + NSYS * k;
+      if (s < a.nsym) {
+        for (int q = 0; q < nvalid; ++q) {
+          const float2 v = sm.m(q, s, i);
+          const float2 pw = lds_el<UT>(sm.A[q], s, i);
+          zf[k].x += v.x;
+          zf[k].y += v.y;
+          swk[k] += pw.x;
+          svk[k] += pw.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (i < a.U) {
+    const size_t ob = (size_t)w * a.zsw;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int s = g + NSYS * k;
+      if (s < a.nsym) {
+        const float inv = 1.0f / swk[k];
+        a.z[ob + (size_t)s * a.U + i] = user_nu ? zf[k] : make_float2(zf[k].x * inv, zf[k].y * inv);
+        if (a.s2) a.s2[ob + (size_t)s * a.U + i] = user_nu ? svk[k] : inv;
+      }
+    }
+  }
+}
+
 // PD systems per work item.
 template <int UT>
 constexpr int sym_pd_per() {
@@ -635,6 +781,44 @@ static hipError_t launch_sym_one(const FwdArgs &a, hipStream_t s) {
 template <int UT, bool FD>
 static hipError_t launch_sym_prec(const FwdArgs &a, int prec, hipStream_t s) {
   return prec == PREC_FP32 ? launch_sym_one<UT, PREC_FP32, FD>(a, s) : launch_sym_one<UT, PREC_BF16X3_NR, FD>(a, s);
+}
+
+template <int UT, int PREC, bool FD, int M>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void eq_symbols_lama_kernel(const FwdArgs a) {
+  __shared__ SymSmem<UT, FD ? 64 / UT : sym_pd_per<UT>()> sm;
+  if constexpr (FD) {
+    fd_sym_lama_task<UT, PREC, M>(a, blockIdx.x, sm);
+  } else {
+    const int w0 = blockIdx.x * sym_pd_per<UT>();
+    pd_sym_lama_task<UT, PREC, M>(a, w0, min(sym_pd_per<UT>(), a.W - w0), sm);
+  }
+}
+
+template <int UT, int PREC, bool FD>
+static hipError_t launch_sym_lama_one(const FwdArgs &a, hipStream_t s) {
+  const int per = FD ? 1 : sym_pd_per<UT>();
+  const dim3 grid((a.W + per - 1) / per), block(64);
+  switch (a.lama_m) {
+    case 2: hipLaunchKernelGGL((eq_symbols_lama_kernel<UT, PREC, FD, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((eq_symbols_lama_kernel<UT, PREC, FD, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((eq_symbols_lama_kernel<UT, PREC, FD, 8>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int UT, bool FD>
+static hipError_t launch_sym_lama_prec(const FwdArgs &a, int prec, hipStream_t s) {
+  return prec == PREC_FP32 ? launch_sym_lama_one<UT, PREC_FP32, FD>(a, s)
+                           : launch_sym_lama_one<UT, PREC_BF16X3_NR, FD>(a, s);
+}
+
+hipError_t launch_symbols_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s) {
+  if (prec != PREC_FP32 && prec != PREC_BF16X3_NR) return hipErrorInvalidValue;
+  if (a.nsym < 1 || a.nsym > symbol_tile(a.U)) return hipErrorInvalidValue;
+  const int UT = ut_for(a.U);
+  if (UT == 16) return fd ? launch_sym_lama_prec<16, true>(a, prec, s) : launch_sym_lama_prec<16, false>(a, prec, s);
+  return fd ? launch_sym_lama_prec<32, true>(a, prec, s) : launch_sym_lama_prec<32, false>(a, prec, s);
 }
 
 int symbol_tile(int U) { return ut_for(U); }

@@ -236,3 +236,21 @@ def test_lama_validation(lib, fd):
         assert lib.eq_fd_lama(None, 2, 16, A, A, None, A, A, A, None) == EINVAL
     else:
         assert lib.eq_pd_lama(None, 2, 16, A, A, A, A, A, None) == EINVAL
+
+
+@pytest.mark.parametrize("fd", [False, True])
+def test_lama_symbols_validation(lib, fd):
+    def call(prob, nsym, t, q, Y=A):
+        if fd:
+            return lib.eq_fd_lama_sym(ctypes.byref(prob), nsym, t, q, A, Y, None, A, A, A, None)
+        return lib.eq_pd_lama_sym(ctypes.byref(prob), nsym, t, q, A, Y, A, A, A, None)
+    prob, _k = _prob()
+    assert call(prob, 0, 2, 16) == EINVAL
+    assert call(prob, 1025, 2, 16) == ENOTSUP
+    assert call(prob, 4, 0, 16) == EINVAL
+    assert call(prob, 4, 2, 32) == EINVAL
+    assert call(prob, 4, 2, 16, Y=None) == EINVAL
+    p2, _k2 = _prob(prec=1)
+    assert call(p2, 4, 2, 16) == ENOTSUP
+    p0, _k0 = _prob(W=0)
+    assert call(p0, 4, 2, 16) == 0

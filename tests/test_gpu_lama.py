@@ -100,3 +100,72 @@ def test_lama_beats_lmmse_on_qpsk():
     mse_l = np.mean(np.abs(zl - b.s) ** 2)
     mse_m = np.mean(np.abs(zm / g - b.s) ** 2)
     assert mse_l < mse_m, (mse_l, mse_m)
+
+
+# ---------------------------------------------------------------- several receive vectors
+SYM_SHAPES = [(30, 256, 16, 8, 14), (6, 130, 24, [0, 60, 130], 40), (9, 37, 5, [0, 5, 20, 37], 3)]
+
+
+def _sym_batch(shape, qam, seed):
+    W, B, U, C, S = shape
+    off = C if isinstance(C, list) else None
+    nc = len(C) - 1 if isinstance(C, list) else C
+    return synth.make_symbol_batch(W, B, U, nc, S, 10.0, MODS[qam], seed=seed, cluster_off=off)
+
+
+def _check_sym(mode, b, t_max, qam, prec, nu=None):
+    from paper_1808_04473_amd import api
+    fn = api.eq_pd_lama_sym if mode == "pd" else api.eq_fd_lama_sym
+    kw = {} if mode == "pd" else {"nu": None if nu is None else dev(nu.astype(np.float32))}
+    z, s2, info = fn(dev(b.H), dev(b.Y), b.n0, b.cluster_off, t_max=t_max, qam=qam, precision=prec,
+                     return_info=True, **kw)
+    torch.cuda.synchronize()
+    z, s2, info = host(z), host(s2), host(info)
+    assert (info == 0).all()
+    rf = oracle.eq_pd_lama if mode == "pd" else oracle.eq_fd_lama
+    worst = 0.0
+    for s in range(b.Y.shape[1]):
+        if mode == "pd":
+            zr, sr = rf(b.H, b.Y[:, s], b.n0, b.cluster_off, t_max, qam)
+        else:
+            zr, sr = rf(b.H, b.Y[:, s], b.n0, b.cluster_off, t_max, qam, nu=nu)
+        ez = max_rel_err(z[:, s], zr)
+        worst = max(worst, ez)
+        assert ez <= TOL_Z[prec], (s, ez)
+        assert max_db_err(s2[:, s], sr) <= TOL_DB
+    return worst
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("qam", [4, 16])
+@pytest.mark.parametrize("t_max", [1, 3])
+@pytest.mark.parametrize("shape", SYM_SHAPES, ids=lambda s: f"W{s[0]}B{s[1]}U{s[2]}S{s[4]}")
+def test_lama_symbols_match_oracle(mode, prec, qam, t_max, shape):
+    """eq_pd_lama_sym / eq_fd_lama_sym: every vector against the oracle's
+    LAMA on that vector alone (z and its own sigma2)."""
+    b = _sym_batch(shape, qam, seed=shape[0] + qam + t_max)
+    worst = _check_sym(mode, b, t_max, qam, prec)
+    print(f"lama sym {mode} {prec} qam{qam} T={t_max} {shape}: z err {worst:.2e}", flush=True)
+
+
+def test_lama_symbols_fd_given_weights():
+    b = _sym_batch((11, 96, 8, 3, 9), 16, seed=51)
+    nu = np.random.default_rng(6).uniform(0.1, 1.0, size=(11, 3, 8))
+    _check_sym("fd", b, 2, 16, "fp32", nu=nu)
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+def test_lama_symbols_non_finite_vector(mode):
+    """A NaN in one receive vector gives NaN for that vector only."""
+    from paper_1808_04473_amd import api
+    b = _sym_batch((6, 64, 8, 2, 5), 16, seed=52)
+    b.Y[2, 3, 17] = np.complex64(complex(np.nan, 0.0))
+    fn = api.eq_pd_lama_sym if mode == "pd" else api.eq_fd_lama_sym
+    z, s2 = fn(dev(b.H), dev(b.Y), b.n0, b.cluster_off, t_max=2, qam=16)
+    torch.cuda.synchronize()
+    z = host(z)
+    assert np.isnan(z[2, 3]).all()
+    keep = np.ones(z.shape[:2], bool)
+    keep[2, 3] = False
+    assert np.isfinite(z[keep]).all()
