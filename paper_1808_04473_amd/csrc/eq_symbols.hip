@@ -418,7 +418,8 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
       if (a.s2) a.s2[(size_t)w * a.U + i] = out_nan ? nanv : o.s2;
     }
     if (live && i == 0 && a.info) a.info[w] = o.bad ? -1 : o.fail;
-  } else {
+    return;
+  }
   SymSolve<UT> r;
   sym_factor<UT>(r, sm, slot, i, a.U);
   const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
@@ -453,7 +454,6 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
       if (a.info) a.info[w] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) enqueue_fp64_sym(a, w);
     }
-  }
   }
 }
 
@@ -536,7 +536,9 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       sm.F[g][i] = out_nan ? make_float2(nanv, nanv) : make_float2(p, p * p * o.s2);
       __syncthreads();
       valu_fuse(nvalid);
-    } else {
+      __syncthreads();
+      continue;
+    }
     SymSolve<UT> r;
     sym_factor<UT>(r, sm, g, i, a.U);
     const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);
@@ -574,7 +576,6 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
       __syncthreads();
       valu_fuse(nvalid);
-    }
     }
     __syncthreads();
   }
