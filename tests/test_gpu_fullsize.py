@@ -121,3 +121,44 @@ def test_large_fp64_queue():
         zr, sr = (oracle.eq_pd if mode == "pd" else oracle.eq_fd)(H[idx], y[idx], np.float32(1e-9), b.cluster_off)
         assert max_rel_err(host(z)[idx], zr) <= TOL_Z["fp32"]
         assert max_db_err(host(s2)[idx], sr) <= TOL_DB
+
+
+def _sampled(data, fn, ref, tol, nsample, seed, **kw):
+    Hn, yn, n0, off, H, y = data
+    W = Hn.shape[0]
+    z, s2, info = fn(H, y, n0, off, return_info=True, **kw)
+    torch.cuda.synchronize()
+    assert int((info & ~(1 << 30)).ne(0).sum().item()) == 0
+    assert bool(torch.isfinite(torch.view_as_real(z)).all().item())
+    assert bool((s2 > 0).all().item())
+    idx = _sample(W, nsample, seed)
+    sel = torch.from_numpy(idx).to(H.device)
+    zr, sr = ref(Hn[idx], yn[idx], n0, off)
+    ez, es = max_rel_err(host(z[sel]), zr), max_db_err(host(s2[sel]), sr)
+    print(f"{fn.__name__} {kw} W={W}: {len(idx)} sampled, z err {ez:.2e}, sigma2 {es:.4f} dB", flush=True)
+    assert ez <= tol and es <= TOL_DB
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("kind", ["zf", "mrc"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_linear_equalisers_at_launch_size(c2_full, c3_full, mode, kind, prec):
+    """ZF and MRC at 38,400 (B=256) and 4,800 (B=1024) systems, sampled."""
+    from paper_1808_04473_amd import api
+    fn = api.eq_pd if mode == "pd" else api.eq_fd
+    rf = oracle.eq_pd_linear if mode == "pd" else oracle.eq_fd_linear
+    for data, n, seed in ((c2_full, 256, 7), (c3_full, 48, 8)):
+        _sampled(data, fn, lambda H, y, n0, off: rf(H, y, n0, off, kind), TOL_Z[prec], n, seed,
+                 precision=prec, equalizer=kind)
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+@pytest.mark.parametrize("t_max", [1, 3])
+def test_lama_at_launch_size(c2_full, c3_full, mode, t_max):
+    """LAMA (16-QAM) at 38,400 (B=256) and 4,800 (B=1024) systems, sampled."""
+    from paper_1808_04473_amd import api
+    fn = api.eq_pd_lama if mode == "pd" else api.eq_fd_lama
+    rf = oracle.eq_pd_lama if mode == "pd" else oracle.eq_fd_lama
+    for data, n, seed in ((c2_full, 256, 9), (c3_full, 48, 10)):
+        _sampled(data, fn, lambda H, y, n0, off: rf(H, y, n0, off, t_max, 16), TOL_Z["fp32"], n, seed,
+                 t_max=t_max, qam=16)
