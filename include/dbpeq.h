@@ -260,6 +260,9 @@ eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypoo
    (else a full round of 64/UT systems of equal U); *out_tasks = work items. */
 eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_shape, int32_t *out_tasks);
 
+/* Frees the plan and every device buffer and graph it holds (a null plan
+   is a no-op).  The plan is gone on return either way; EQ_EHIP reports that
+   one of the releases failed. */
 eq_status eq_plan_destroy(eq_plan *plan);
 
 const char *eq_status_string(eq_status s);

@@ -451,8 +451,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.eq_plan_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _check("eq_plan_destroy", self._lib.eq_plan_destroy(h))
 
     def __del__(self):
         try:

@@ -31,7 +31,6 @@ struct BSmem {
 template <int UT, class Seg>
 __device__ __forceinline__ float round_backward(const BwdArgs &a, BSmem<UT> &sm, LocalSolve<UT> &r,
                                                 int nvalid, Seg seg, float2 gzc, float gsc) {
-  constexpr int RPB = 8 * (64 / UT);
   const int lane = lane_id();
   const int sme = lane / UT, i = lane % UT;
   const int col = lane % UT;

@@ -90,7 +90,8 @@ eq_status upload_tasks(eq_plan *p, int half) {
   std::vector<RTask> tasks;
   std::vector<int32_t> order;
   build_tasks(*p, half, tasks, order);
-  if (p->d_tasks) hipFree(p->d_tasks);
+  // the previous table: a failed free leaves nothing this call could repair
+  if (p->d_tasks) (void)hipFree(p->d_tasks);
   p->d_tasks = nullptr;
   if (hipMalloc(&p->d_tasks, sizeof(RTask) * tasks.size()) != hipSuccess) return EQ_ENOMEM;
   if (hipMemcpy(p->d_tasks, tasks.data(), sizeof(RTask) * tasks.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -200,8 +201,16 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
   }
   const int waves[] = {1, 2, 4, 8};
   const int nh = p->fd ? 1 : 2;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EQ_EHIP;
+  // destroyed on every exit, the error returns of the loop included
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  if (hipEventCreate(&ev.e[0]) != hipSuccess || hipEventCreate(&ev.e[1]) != hipSuccess) return EQ_EHIP;
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
   float best = 1e30f;
   int bg = cus * 2, bh = 0;
   for (int hf = 0; hf < nh; ++hf) {
@@ -212,12 +221,12 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
       RaggedArgs a = make_args(p, H, y, z, s2, info);
       float tmin = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
-        hipEventRecord(e0, s);
+        if (hipEventRecord(e0, s) != hipSuccess) return EQ_EHIP;
         if (enqueue(p, a, grid, s) != hipSuccess) return EQ_EHIP;
-        hipEventRecord(e1, s);
+        if (hipEventRecord(e1, s) != hipSuccess) return EQ_EHIP;
         if (hipEventSynchronize(e1) != hipSuccess) return EQ_EHIP;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return EQ_EHIP;
         tmin = ms < tmin ? ms : tmin;
       }
       if (tmin < best) {
@@ -227,8 +236,6 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   p->grid = bg;
   p->half = bh;
   p->tuned = true;
@@ -239,8 +246,8 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
 }
 
 void drop_graph(eq_plan *p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
 }
@@ -364,7 +371,7 @@ eq_status eq_plan_execute(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return EQ_EHIP;
     }
     p->graph = g;
@@ -391,14 +398,13 @@ eq_status eq_plan_describe(const eq_plan *p, int32_t *out_waves, int32_t *out_ta
 eq_status eq_plan_destroy(eq_plan *p) {
   if (!p) return EQ_OK;
   drop_graph(p);
-  if (p->cap) hipStreamDestroy(p->cap);
-  if (p->d_sys) hipFree(p->d_sys);
-  if (p->d_offs) hipFree(p->d_offs);
-  if (p->d_tasks) hipFree(p->d_tasks);
-  if (p->d_order) hipFree(p->d_order);
-  if (p->d_scratch) hipFree(p->d_scratch);
+  // release everything, then report whether any release failed
+  bool ok = true;
+  if (p->cap) ok &= hipStreamDestroy(p->cap) == hipSuccess;
+  for (void *d : {(void *)p->d_sys, (void *)p->d_offs, (void *)p->d_tasks, (void *)p->d_order, (void *)p->d_scratch})
+    if (d) ok &= hipFree(d) == hipSuccess;
   delete p;
-  return EQ_OK;
+  return ok ? EQ_OK : EQ_EHIP;
 }
 
 }  // extern "C"

@@ -552,7 +552,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       // weight and variance term of (cluster g, user i)
       sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
       __syncthreads();
-      const int kk = lane >> 4, cs = lane & 15;
+      const int kk = lane >> 4;
       for (int q = 0; q < nvalid; ++q) {
         f4 zr, zi;
         sym_mfma16(sm, q, zr, zi);
@@ -565,7 +565,6 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
           svk[rr] += fv.y;
         }
       }
-      (void)cs;
     } else {
       // weighted estimates replace the group's matched filters, row by row
       // (each row is read by the whole group before its lane i overwrites it)
