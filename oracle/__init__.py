@@ -29,6 +29,7 @@ from .lmmse import (local_statistics, lmmse_estimate, lmmse_error_variance,
                     lmmse_error_variance_simplified, cond_estimate, eq_pd, eq_fd,
                     optimal_fusion_weights, eq_centralized, eq_pd_symbols, eq_fd_symbols)
 from .linear import (mrc_estimate, mrc_error_variance, zf_estimate, zf_error_variance,
+                     lmmse_unbiased_gain, lmmse_unbiased_estimate, lmmse_unbiased_error_variance,
                      eq_pd_linear, eq_fd_linear)
 from .lama import (qam_points, posterior_mean_var, lama_pd, lama_original, eq_pd_lama,
                    eq_fd_lama)

@@ -6,6 +6,12 @@ statistics (G, y^MRC) of eq. (fullMRC):
         sigma^2 = diag( D^{-1} G D^{-H} N0 + (D^{-1} G - I)(D^{-1} G - I)^H E_s ),
         D = diag(G);
   ZF    z = G^{-1} y^MRC,  sigma^2 = N0 diag(G^{-1}).
+The unbiased L-MMSE option is not in the paper (Section III-A gives the
+biased estimate only); read here as the L-MMSE estimate scaled to unit gain:
+with W = (G + rho I)^{-1}, user u sees the gain mu_u = [W G]_uu, and
+  z = diag(mu)^{-1} W y^MRC,
+  sigma^2 = diag( E G E^H N0 + (E G - I)(E G - I)^H E_s ),  E = diag(mu)^{-1} W,
+the Section III-A variance of a linear equaliser E acting on y^MRC.
 In the FD architecture (Section IV-A) every cluster applies the same
 equaliser to its own statistics (G_c, y_c^MRC), and the fusion tree combines
 the local estimates with the weights of Lemma 1 (eq. (opt_fusion)) or given
@@ -16,7 +22,7 @@ import numpy as np
 from .lmmse import _c128, _herm, lmmse_error_variance, lmmse_estimate, local_statistics, \
     optimal_fusion_weights
 
-KINDS = ("lmmse", "zf", "mrc")
+KINDS = ("lmmse", "zf", "mrc", "lmmse_unbiased")
 
 
 def mrc_estimate(G, m):
@@ -52,6 +58,37 @@ def zf_error_variance(G, n0):
     return float(n0) * np.real(np.diagonal(Gi, axis1=-2, axis2=-1)).copy()
 
 
+def _unbiased_matrix(G, n0, es):
+    """E = diag(mu)^{-1} W with W = (G + rho I)^{-1}, mu_u = [W G]_uu."""
+    G = _c128(G)
+    U = G.shape[-1]
+    W = np.linalg.inv(G + (float(n0) / float(es)) * np.eye(U))
+    mu = np.real(np.diagonal(W @ G, axis1=-2, axis2=-1))
+    return W / mu[..., :, None], mu
+
+
+def lmmse_unbiased_gain(G, n0, es=1.0):
+    """mu_u = [(G + rho I)^{-1} G]_uu, the gain of user u in the biased L-MMSE estimate."""
+    return _unbiased_matrix(G, n0, es)[1]
+
+
+def lmmse_unbiased_estimate(G, m, n0, es=1.0):
+    """z = diag(mu)^{-1} (G + rho I)^{-1} y^MRC (unit gain for every user)."""
+    E, _ = _unbiased_matrix(G, n0, es)
+    return (E @ _c128(m)[..., None])[..., 0]
+
+
+def lmmse_unbiased_error_variance(G, n0, es=1.0):
+    """The Section III-A error variance of the equaliser E = diag(mu)^{-1} W,
+    term by term: diag( E G E^H N0 + (E G - I)(E G - I)^H E_s )."""
+    G = _c128(G)
+    E, _ = _unbiased_matrix(G, n0, es)
+    EG = E @ G
+    I = np.eye(G.shape[-1])
+    S = E @ G @ _herm(E) * float(n0) + (EG - I) @ _herm(EG - I) * float(es)
+    return np.real(np.diagonal(S, axis1=-2, axis2=-1)).copy()
+
+
 def _equalise(kind, G, m, n0, es):
     if kind == "lmmse":
         return lmmse_estimate(G, m, n0, es), lmmse_error_variance(G, n0, es)
@@ -59,11 +96,13 @@ def _equalise(kind, G, m, n0, es):
         return zf_estimate(G, m), zf_error_variance(G, n0)
     if kind == "mrc":
         return mrc_estimate(G, m), mrc_error_variance(G, n0, es)
+    if kind == "lmmse_unbiased":
+        return lmmse_unbiased_estimate(G, m, n0, es), lmmse_unbiased_error_variance(G, n0, es)
     raise ValueError(f"equaliser {kind!r} is not one of {KINDS}")
 
 
 def eq_pd_linear(H, y, n0, cluster_off, kind, es=1.0):
-    """PD equalisation with `kind` in ("lmmse", "zf", "mrc"): the adder tree
+    """PD equalisation with `kind` in KINDS: the adder tree
     sums the local statistics (eq. (fullMRC)) and the centralised unit applies
     the equaliser.  Returns z [W][U], sigma2 [W][U]."""
     Gc, mc = local_statistics(H, y, cluster_off)

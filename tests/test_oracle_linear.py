@@ -1,7 +1,7 @@
-"""Pins of the MRC / ZF oracle (Section III-A, Section IV-A, Lemma 4) to what
-the mathematics fixes: noise-free recovery, explicit loops on tiny inputs,
-Monte-Carlo error variances, an exact fusion identity and the finite-size
-expectation behind Lemma 4."""
+"""Pins of the MRC / ZF / unbiased L-MMSE oracle (Section III-A, Section IV-A,
+Lemma 4) to what the mathematics fixes: noise-free recovery, explicit loops
+on tiny inputs, Monte-Carlo error variances and gains, exact identities and
+closed forms, and the finite-size expectation behind Lemma 4."""
 import numpy as np
 import pytest
 
@@ -45,10 +45,11 @@ def test_mrc_explicit_loops():
             assert abs(s2[w, u] - (n0 / guu + es * off / guu ** 2)) < 1e-12
 
 
-@pytest.mark.parametrize("kind", ["zf", "mrc"])
+@pytest.mark.parametrize("kind", ["zf", "mrc", "lmmse_unbiased"])
 def test_error_variance_monte_carlo(kind):
     """E|z - s|^2 over symbols and noise for one fixed H matches the
-    Section III-A variance (ZF: noise only; MRC: noise and interference)."""
+    Section III-A variance (ZF: noise only; MRC and unbiased L-MMSE: noise
+    and interference)."""
     rng = np.random.default_rng(3)
     B, U, N, n0 = 10, 3, 200000, 0.2
     H = _h(rng, 1, B, U)[0]
@@ -77,7 +78,7 @@ def test_fd_mrc_with_gram_weights_equals_pd_mrc():
     np.testing.assert_allclose(zf, zp, rtol=1e-12)
 
 
-@pytest.mark.parametrize("kind", ["zf", "mrc", "lmmse"])
+@pytest.mark.parametrize("kind", ["zf", "mrc", "lmmse", "lmmse_unbiased"])
 def test_one_cluster_fd_equals_pd(kind):
     rng = np.random.default_rng(5)
     H = _h(rng, 4, 12, 3)
@@ -115,3 +116,59 @@ def test_fd_zf_sinr_finite_size_expectation():
     assert abs(sinr / expect - 1) < 0.01, (sinr, expect)
     # and Lemma 4's large-system value is the limit of that expectation
     assert abs(expect * n0 - (1 - C * U / B) - C / B) < 1e-12
+
+
+def test_unbiased_gain_identity():
+    """(G + rho I)^{-1} G = I - rho (G + rho I)^{-1}, so the gain of the biased
+    L-MMSE estimate is mu_u = 1 - rho d_u = 1 - sigma2_u / E_s; the unbiased
+    estimate is z_u / mu_u with variance sigma2_u / mu_u (both from the
+    biased L-MMSE oracle), and E_s / sigma2_unbiased = E_s / sigma2 - 1."""
+    rng = np.random.default_rng(7)
+    H = _h(rng, 6, 20, 5)
+    y = rng.standard_normal((6, 20)) + 1j * rng.standard_normal((6, 20))
+    n0, es = 0.08, 1.3
+    G = np.conj(np.swapaxes(H, 1, 2)) @ H
+    zb, sb = oracle.eq_pd(H, y, n0, [0, 20], es=es)
+    mu = oracle.lmmse_unbiased_gain(G, n0, es)
+    np.testing.assert_allclose(mu, 1.0 - sb / es, rtol=1e-12)
+    zu, su = oracle.eq_pd_linear(H, y, n0, [0, 9, 20], "lmmse_unbiased", es=es)
+    np.testing.assert_allclose(zu, zb / mu, rtol=1e-11)
+    np.testing.assert_allclose(su, sb / mu, rtol=1e-11)
+    np.testing.assert_allclose(es / su, es / sb - 1.0, rtol=1e-10)
+
+
+def test_unbiased_orthogonal_columns_is_zf():
+    """H^H H = alpha I: mu = alpha / (alpha + rho), so the unbiased L-MMSE
+    estimate is y^MRC / alpha with variance N0 / alpha, the ZF result."""
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 4)) + 1j * rng.standard_normal((12, 4)))
+    H = (1.7 * Q)[None]
+    y = (rng.standard_normal(12) + 1j * rng.standard_normal(12))[None]
+    n0 = 0.3
+    z, s2 = oracle.eq_pd_linear(H, y, n0, [0, 12], "lmmse_unbiased")
+    m = (np.conj(H[0]).T @ y[0])
+    np.testing.assert_allclose(z[0], m / 1.7 ** 2, rtol=1e-12)
+    np.testing.assert_allclose(s2[0], np.full(4, n0 / 1.7 ** 2), rtol=1e-12)
+    zz, sz = oracle.eq_pd_linear(H, y, n0, [0, 12], "zf")
+    np.testing.assert_allclose(z, zz, rtol=1e-12)
+    np.testing.assert_allclose(s2, sz, rtol=1e-12)
+
+
+def test_unbiased_unit_gain_monte_carlo():
+    """Regressing the estimate of user u on its symbol over symbols and noise
+    gives slope 1 for the unbiased estimate and mu_u for the biased one."""
+    rng = np.random.default_rng(9)
+    B, U, N, n0 = 8, 3, 200000, 0.4
+    H = _h(rng, 1, B, U)[0]
+    s = (rng.choice([-1, 1], (N, U)) + 1j * rng.choice([-1, 1], (N, U))) / np.sqrt(2)
+    n = (rng.standard_normal((N, B)) + 1j * rng.standard_normal((N, B))) * np.sqrt(n0 / 2)
+    y = s @ H.T + n
+    Hb = np.broadcast_to(H, (N, B, U))
+    zu, _ = oracle.eq_pd_linear(Hb, y, n0, [0, B], "lmmse_unbiased")
+    zb, _ = oracle.eq_pd_linear(Hb, y, n0, [0, B], "lmmse")
+    mu = oracle.lmmse_unbiased_gain(np.conj(H).T @ H, n0)
+    assert np.all(mu < 0.95)
+    slope_u = np.sum(np.conj(s) * zu, axis=0) / np.sum(np.abs(s) ** 2, axis=0)
+    slope_b = np.sum(np.conj(s) * zb, axis=0) / np.sum(np.abs(s) ** 2, axis=0)
+    np.testing.assert_allclose(slope_u, np.ones(U), atol=0.01)
+    np.testing.assert_allclose(slope_b, mu, atol=0.01)
