@@ -278,13 +278,14 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
             pl.close()
     del pools
 
-    # ZF and MRC on the headline systems (same Gram pass, different solve)
+    # ZF, MRC and unbiased L-MMSE on the headline systems (same Gram pass,
+    # different solve or output scaling)
     samp2 = np.arange(0, Hn.shape[0], Hn.shape[0] // 48)
     sel2 = torch.from_numpy(samp2).to(dev)
     for mode in ("pd", "fd"):
         fn = api.eq_pd if mode == "pd" else api.eq_fd
         rf = oracle.eq_pd_linear if mode == "pd" else oracle.eq_fd_linear
-        for kind in ("zf", "mrc"):
+        for kind in ("zf", "mrc", "lmmse_unbiased"):
             for prec in ("fp32", "bf16x3"):
                 t = _timed(lambda: fn(H, y, n0, off, precision=prec, equalizer=kind), steps, 3)
                 z, s2 = fn(H, y, n0, off, precision=prec, equalizer=kind)

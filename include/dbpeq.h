@@ -92,9 +92,19 @@ typedef enum {
                sigma2_u = N0 / G_uu + E_s sum_{k != u} |G_uk|^2 / G_uu^2
                (the diagonal of the Section III-A MRC variance); no
                factorisation and no FP64 re-solve; EQ_FP32 or EQ_BF16X3 only.
+     EQ_LMMSE_UNBIASED
+               the L-MMSE estimate scaled to unit gain (the paper defines
+               only the biased one): user u's gain in the L-MMSE estimate is
+               mu_u = [(G + rho I)^{-1} G]_uu = 1 - sigma2_u / E_s, and the
+               outputs are z_u / mu_u and sigma2_u / mu_u (sigma2 of
+               EQ_LMMSE), so that E_s / sigma2 is the unbiased SINR.  FD
+               scales every cluster's estimate before the fusion, whose
+               weights then come from the scaled variances.  EQ_FP32 or
+               EQ_BF16X3 only: the refinement step improves z, not the
+               diagonal of the inverse that gives mu.
    The multi-vector calls take every equaliser; the backward calls and the
    ragged plans are L-MMSE only. */
-typedef enum { EQ_LMMSE = 0, EQ_ZF = 1, EQ_MRC = 2 } eq_equalizer;
+typedef enum { EQ_LMMSE = 0, EQ_ZF = 1, EQ_MRC = 2, EQ_LMMSE_UNBIASED = 3 } eq_equalizer;
 
 /* Shared description of a batch of W systems. */
 typedef struct {

@@ -112,7 +112,7 @@ def _check(fn: str, st: int):
         raise EqError(fn, st)
 
 
-EQUALIZERS = {"lmmse": 0, "zf": 1, "mrc": 2}
+EQUALIZERS = {"lmmse": 0, "zf": 1, "mrc": 2, "lmmse_unbiased": 3}
 
 
 def make_problem(W, B, U, cluster_off, n0, es=1.0, precision="fp32", equalizer="lmmse"):
@@ -164,7 +164,7 @@ def _cached_workspace(prob: EqProblem, device) -> torch.Tensor:
 def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
           ws=None, equalizer="lmmse"):
     """Partially decentralised equalisation of W systems (L-MMSE by default,
-    or equalizer="zf" / "mrc"): (z [W][U] c64, sigma2 [W][U] f32).
+    or equalizer="zf" / "mrc" / "lmmse_unbiased"): (z [W][U] c64, sigma2 [W][U] f32).
 
     `out` = (z, sigma2, info) and `ws` (uint8 workspace) may be preallocated."""
     lib = load_library()
@@ -186,7 +186,7 @@ def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, ou
 
 def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
           out=None, ws=None, equalizer="lmmse"):
-    """Fully decentralised equalisation (L-MMSE, "zf" or "mrc" per cluster);
+    """Fully decentralised equalisation (L-MMSE, "zf", "mrc" or "lmmse_unbiased" per cluster);
     nu [W][C][U] float32 user weights or None (optimal)."""
     lib = load_library()
     H, y = _check_inputs(H, y)
@@ -254,14 +254,14 @@ def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws
 
 def eq_pd_sym(H, Y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
               ws=None, equalizer="lmmse"):
-    """PD L-MMSE (or "zf" / "mrc") of S receive vectors per channel matrix: H [W][B][U],
+    """PD L-MMSE (or "zf" / "mrc" / "lmmse_unbiased") of S receive vectors per channel matrix: H [W][B][U],
     Y [W][S][B] -> (Z [W][S][U] c64, sigma2 [W][U] f32).  Precision "fp32" or "bf16x3"."""
     return _sym_call(False, H, Y, n0, cluster_off, None, precision, es, return_info, out, ws, equalizer)
 
 
 def eq_fd_sym(H, Y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=False,
               out=None, ws=None, equalizer="lmmse"):
-    """FD L-MMSE (or "zf" / "mrc") of S receive vectors per channel matrix (weights as eq_fd)."""
+    """FD L-MMSE (or "zf" / "mrc" / "lmmse_unbiased") of S receive vectors per channel matrix (weights as eq_fd)."""
     return _sym_call(True, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws, equalizer)
 
 

@@ -26,8 +26,12 @@ eq_status check_problem(const eq_problem *p) {
   if (!isfinite(p->n0) || !(p->n0 > 0.f)) return EQ_EINVAL;
   if (!isfinite(p->es) || !(p->es > 0.f)) return EQ_EINVAL;
   if (p->precision < EQ_FP32 || p->precision > EQ_BF16X3) return EQ_EINVAL;
-  if (p->equalizer < EQ_LMMSE || p->equalizer > EQ_MRC) return EQ_EINVAL;
-  if (p->equalizer == EQ_MRC && p->precision != EQ_FP32 && p->precision != EQ_BF16X3) return EQ_ENOTSUP;
+  if (p->equalizer < EQ_LMMSE || p->equalizer > EQ_LMMSE_UNBIASED) return EQ_EINVAL;
+  // MRC has no factor to refine; the unbiased L-MMSE gain comes from diag(A^{-1}),
+  // which a refinement step does not improve
+  if ((p->equalizer == EQ_MRC || p->equalizer == EQ_LMMSE_UNBIASED) && p->precision != EQ_FP32 &&
+      p->precision != EQ_BF16X3)
+    return EQ_ENOTSUP;
   const float rho = p->n0 / p->es;
   if (!isfinite(rho) || !(rho > 0.f)) return EQ_EINVAL;
   return EQ_OK;
@@ -46,8 +50,11 @@ void fill_fwd(FwdArgs &a, const eq_problem *p) {
   a.C = p->C;
   a.n0 = p->n0;
   a.es = p->es;
-  // ZF is the L-MMSE solve with rho = 0; MRC stores G without a shift
-  a.rho = p->equalizer == EQ_LMMSE ? p->n0 / p->es : 0.f;
+  // ZF is the L-MMSE solve with rho = 0; MRC stores G without a shift; the
+  // unbiased L-MMSE divides the L-MMSE outputs by their gain
+  const bool lmmse = p->equalizer == EQ_LMMSE || p->equalizer == EQ_LMMSE_UNBIASED;
+  a.rho = lmmse ? p->n0 / p->es : 0.f;
+  a.ub = p->equalizer == EQ_LMMSE_UNBIASED ? 1.0f / p->es : 0.f;
   a.eqz = p->equalizer;
   for (int c = 0; c <= p->C; ++c) a.off[c] = (uint16_t)p->cluster_off[c];
   a.spw = fd_spw(ut_for(p->U), p->C);

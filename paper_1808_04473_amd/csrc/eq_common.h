@@ -10,7 +10,7 @@ namespace dbpeq {
 enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_BF16X3_NR = 3 };
 
 // Equaliser of the forward calls (the eq_equalizer values).
-enum Eqz { EQZ_LMMSE = 0, EQZ_ZF = 1, EQZ_MRC = 2 };
+enum Eqz { EQZ_LMMSE = 0, EQZ_ZF = 1, EQZ_MRC = 2, EQZ_LMMSE_UB = 3 };
 
 // Forms that run the refinement step with the FP32 residual y - H z.
 constexpr bool refines(int prec) { return prec == PREC_BF16 || prec == PREC_BF16X3; }
@@ -30,6 +30,8 @@ struct FwdArgs {
   int32_t *fb_list;     // queued systems
   int32_t W, B, U, C;
   float n0, rho, es;
+  float ub;             // 1/E_s for the unbiased L-MMSE, else 0: the outputs are
+                        // divided by the gain 1 - sigma2 * ub (exactly 1 at ub = 0)
   int32_t spw;          // FD: subcarriers per wave
   // receive vectors: nsym per channel matrix in this launch (1 for the
   // single-vector entry points), y + w*ysw is the first of subcarrier w,

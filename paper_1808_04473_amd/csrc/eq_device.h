@@ -785,4 +785,9 @@ __device__ __forceinline__ float inv_diag(const Factor<UT> &f) {
 
 __device__ __forceinline__ bool finite2(float2 v) { return isfinite(v.x) && isfinite(v.y); }
 
+// Unbiased L-MMSE: the L-MMSE estimate of user u has gain
+// mu_u = [(G + rho I)^{-1} G]_uu = 1 - rho d_u = 1 - sigma2_u / E_s; returns
+// 1 / mu_u for ub = 1/E_s, and exactly 1 for ub = 0 (biased L-MMSE, ZF).
+__device__ __forceinline__ float unbias_factor(float s2, float ub) { return 1.0f / (1.0f - s2 * ub); }
+
 }  // namespace dbpeq

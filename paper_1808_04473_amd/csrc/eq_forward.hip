@@ -90,8 +90,9 @@ __device__ __forceinline__ void pd_task(const FwdArgs &a, int w0, int nvalid, SM
   if (live) {
     if (i < a.U) {
       const float nanv = __int_as_float(0x7fc00000);
-      a.z[(size_t)w * a.U + i] = r.bad ? make_float2(nanv, nanv) : r.z;
-      if (a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d;
+      const float s2 = a.n0 * r.d, k = unbias_factor(s2, a.ub);
+      a.z[(size_t)w * a.U + i] = r.bad ? make_float2(nanv, nanv) : make_float2(r.z.x * k, r.z.y * k);
+      if (a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : s2 * k;
     }
     if (i == 0) {
       if (a.info) a.info[w] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
@@ -155,9 +156,11 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, SM &
       if (a.info) a.info[(size_t)w * C + c] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) sm.routed[wl] = 1;
     }
-    const float s2c = a.n0 * r.d;
+    // local estimate and variance (scaled to unit gain for the unbiased L-MMSE)
+    const float k = unbias_factor(a.n0 * r.d, a.ub);
+    const float s2c = a.n0 * r.d * k;
     __syncthreads();
-    sm.F[sme][i] = live ? (r.bad ? make_float4(nanv, nanv, nanv, 1.f) : make_float4(r.z.x, r.z.y, s2c, 1.f))
+    sm.F[sme][i] = live ? (r.bad ? make_float4(nanv, nanv, nanv, 1.f) : make_float4(r.z.x * k, r.z.y * k, s2c, 1.f))
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 

@@ -39,7 +39,7 @@ struct F64Smem {
 // status.
 template <class Off, class Info>
 __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const float2 *__restrict__ yw,
-                            int U, int nclus, Off off, double n0, double rho, bool fd,
+                            int U, int nclus, Off off, double n0, double rho, double ub, bool fd,
                             const float *nu_w, float2 *zw, float *s2w, Info on_info,
                             int nsym, size_t ys, size_t zs) {
   const int tid = threadIdx.x;
@@ -96,13 +96,15 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
       }
     }
     __syncthreads();
-    // error variance and fusion weight of user u
-    double wgt = 1.0;
+    // error variance and fusion weight of user u (estimate and variance
+    // divided by the gain 1 - sigma2 ub: the unbiased L-MMSE, 1 at ub = 0)
+    double wgt = 1.0, kub = 1.0;
     if (tid < U) {
       const int u = tid;
       double d = 0.0;
       for (int j = u; j < U; ++j) d += sm.X[j][u].x * sm.X[j][u].x + sm.X[j][u].y * sm.X[j][u].y;
-      const double s2 = n0 * d;
+      kub = 1.0 / (1.0 - n0 * d * ub);
+      const double s2 = n0 * d * kub;
       if (fd) {
         if (nu_w) {
           wgt = nu_w[(size_t)c * U + u];
@@ -150,6 +152,8 @@ __device__ void fp64_system(F64Smem &sm, const float2 *__restrict__ Hw, const fl
           z.x += sm.X[j][u].x * sm.t[j].x + sm.X[j][u].y * sm.t[j].y;
           z.y += sm.X[j][u].x * sm.t[j].y - sm.X[j][u].y * sm.t[j].x;
         }
+        z.x *= kub;
+        z.y *= kub;
         if (fd) {
           const Dc prev = c == 0 ? Dc{0.0, 0.0} : sm.Z[s][u];
           sm.Z[s][u] = {prev.x + wgt * z.x, prev.y + wgt * z.y};
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
       a.info[ii] = fail | (a.info[ii] & EQ_INFO_FP64);
     };
     fp64_system(sm, a.H + (size_t)w * HB, a.y + (size_t)w * a.ysw, a.U, FD ? a.C : 1, off,
-                (double)a.n0, rho, FD, a.nu ? a.nu + (size_t)w * a.C * a.U : nullptr,
+                (double)a.n0, rho, (double)a.ub, FD, a.nu ? a.nu + (size_t)w * a.C * a.U : nullptr,
                 a.z + (size_t)w * a.zsw, a.s2 ? a.s2 + (size_t)w * a.U : nullptr, info, a.nsym,
                 (size_t)a.B, (size_t)a.U);
   }
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) 
       if (fail && !worst) worst = fail;
     };
     fp64_system(sm, a.Hpool + d.h_off, a.ypool + d.y_off, d.U, FD ? d.C : 1, off, (double)d.n0,
-                (double)d.n0 / (double)a.es, FD, nullptr, a.zpool + d.z_off,
+                (double)d.n0 / (double)a.es, 0.0, FD, nullptr, a.zpool + d.z_off,
                 a.s2pool ? a.s2pool + d.z_off : nullptr, info, 1, 0, 0);
     if (threadIdx.x == 0 && a.info) a.info[k] = worst | EQ_INFO_FP64;
   }

@@ -426,8 +426,13 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
   const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
   const int w = w0 + g;
   const float nanv = __int_as_float(0x7fc00000);
+  // gain factor of user i (1 unless the unbiased L-MMSE)
+  const float ku = unbias_factor(a.n0 * r.d, a.ub);
   if constexpr (UT == 16) {
-    // one system at a time on MFMA; slot q holds system w0 + q
+    // one system at a time on MFMA; slot q holds system w0 + q.  Lane
+    // (kk, c) writes users 4 kk + r, whose factors it reads from F (the
+    // barrier inside the first product orders these writes before the reads)
+    sm.F[g][i] = make_float2(ku, 0.f);
     const unsigned long long badm = __ballot(r.bad);
     const int kk = lane >> 4, c = lane & 15;
     for (int q = 0; q < nvalid; ++q) {
@@ -438,18 +443,19 @@ __device__ __forceinline__ void pd_sym_task(const FwdArgs &a, int w0, int nvalid
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int u = 4 * kk + rr;
-        if (c < a.nsym && u < a.U) zw[u] = bq ? make_float2(nanv, nanv) : make_float2(zr[rr], zi[rr]);
+        const float kq = sm.F[q][u].x;
+        if (c < a.nsym && u < a.U) zw[u] = bq ? make_float2(nanv, nanv) : make_float2(zr[rr] * kq, zi[rr] * kq);
       }
     }
   } else {
     float2 *zw = a.z + (size_t)w * a.zsw;
     for (int s = 0; s < a.nsym; ++s) {
       const float2 z = sym_apply<UT>(r, sm, slot, s);
-      if (live && i < a.U) zw[(size_t)s * a.U + i] = r.bad ? make_float2(nanv, nanv) : z;
+      if (live && i < a.U) zw[(size_t)s * a.U + i] = r.bad ? make_float2(nanv, nanv) : make_float2(z.x * ku, z.y * ku);
     }
   }
   if (live) {
-    if (i < a.U && a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d;
+    if (i < a.U && a.s2) a.s2[(size_t)w * a.U + i] = r.bad ? nanv : a.n0 * r.d * ku;
     if (i == 0) {
       if (a.info) a.info[w] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
       if (routed) enqueue_fp64_sym(a, w);
@@ -475,12 +481,15 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
   const int C = a.C;
   const bool user_nu = a.nu != nullptr;
   const float nanv = __int_as_float(0x7fc00000);
+  // F[g][i] = (weight of cluster g's estimate of user i, its term of tk):
+  // tk sums the weights (optimal fusion: the fused variance is 1 / tk) or,
+  // with given weights, nu^2 sigma2_c (the fused variance itself)
   float2 zf[KS];
-  float swk[UT == 16 ? 4 : 1], svk[UT == 16 ? 4 : 1];
+  float tk[UT == 16 ? 4 : 1];
 #pragma unroll
   for (int k = 0; k < KS; ++k) zf[k] = make_float2(0.f, 0.f);
 #pragma unroll
-  for (int k = 0; k < (UT == 16 ? 4 : 1); ++k) { swk[k] = 0.f; svk[k] = 0.f; }
+  for (int k = 0; k < (UT == 16 ? 4 : 1); ++k) tk[k] = 0.f;
   bool routed_any = false;
   // MRC keeps the sums in the (lane / UT, lane % UT) layout at every width
   constexpr bool mrc = MRC;
@@ -498,11 +507,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
         }
       }
     }
-    for (int q = 0; q < nvalid; ++q) {
-      const float2 v = sm.F[q][i];
-      swk[0] += v.x;
-      svk[0] += v.y;
-    }
+    for (int q = 0; q < nvalid; ++q) tk[0] += sm.F[q][i].y;
   };
 
   for (int base = 0; base < C; base += NSYS) {
@@ -533,7 +538,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
         const float2 mv = sm.m(g, s, i);
         sm.m(g, s, i) = out_nan ? make_float2(nanv, nanv) : make_float2(q * mv.x, q * mv.y);
       }
-      sm.F[g][i] = out_nan ? make_float2(nanv, nanv) : make_float2(p, p * p * o.s2);
+      sm.F[g][i] = out_nan ? make_float2(nanv, nanv) : make_float2(p, user_nu ? p * p * o.s2 : p);
       __syncthreads();
       valu_fuse(nvalid);
       __syncthreads();
@@ -545,12 +550,17 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
     const bool routed = live && !r.bad && (r.fail != 0 || !(kappa <= EQ_COND_LIMIT));
     if (live && i == 0 && a.info) a.info[(size_t)w * C + c] = (r.bad ? -1 : r.fail) | (routed ? EQ_INFO_FP64 : 0);
     routed_any |= __ballot(routed) != 0ull;
-    const float s2c = a.n0 * r.d;
+    // local variance (of the estimate scaled to unit gain for the unbiased
+    // L-MMSE: estimate and variance times ku) and fusion weight p; the
+    // estimate's weight is p ku
+    const float ku = unbias_factor(a.n0 * r.d, a.ub);
+    const float s2c = a.n0 * r.d * ku;
     float p = 0.f;
     if (live && i < a.U) p = user_nu ? a.nu[((size_t)w * C + c) * a.U + i] : 1.0f / s2c;
+    const float pz = p * ku;
+    const float2 fterm = r.bad ? make_float2(nanv, nanv) : make_float2(pz, user_nu ? p * p * s2c : p);
     if constexpr (UT == 16) {
-      // weight and variance term of (cluster g, user i)
-      sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
+      sm.F[g][i] = fterm;
       __syncthreads();
       const int kk = lane >> 4;
       for (int q = 0; q < nvalid; ++q) {
@@ -561,8 +571,7 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
           const float2 fv = sm.F[q][4 * kk + rr];
           zf[rr].x += fv.x * zr[rr];
           zf[rr].y += fv.x * zi[rr];
-          swk[rr] += fv.x;
-          svk[rr] += fv.y;
+          tk[rr] += fv.y;
         }
       }
     } else {
@@ -570,9 +579,9 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
       // (each row is read by the whole group before its lane i overwrites it)
       for (int s = 0; s < a.nsym; ++s) {
         const float2 z = sym_apply<UT>(r, sm, g, s);
-        sm.m(g, s, i) = r.bad ? make_float2(nanv, nanv) : make_float2(p * z.x, p * z.y);
+        sm.m(g, s, i) = r.bad ? make_float2(nanv, nanv) : make_float2(pz * z.x, pz * z.y);
       }
-      sm.F[g][i] = r.bad ? make_float2(nanv, nanv) : make_float2(p, p * p * s2c);
+      sm.F[g][i] = fterm;
       __syncthreads();
       valu_fuse(nvalid);
     }
@@ -587,19 +596,19 @@ __device__ __forceinline__ void fd_sym_task(const FwdArgs &a, int w, SM &sm) {
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int u = 4 * kk + rr;
-      const float inv = 1.0f / swk[rr];
+      const float inv = 1.0f / tk[rr];
       if (cs < a.nsym && u < a.U)
         zw[(size_t)cs * a.U + u] = user_nu ? zf[rr] : make_float2(zf[rr].x * inv, zf[rr].y * inv);
-      if (cs == 0 && u < a.U && a.s2) a.s2[(size_t)w * a.U + u] = user_nu ? svk[rr] : inv;
+      if (cs == 0 && u < a.U && a.s2) a.s2[(size_t)w * a.U + u] = user_nu ? tk[rr] : inv;
     }
   } else if (i < a.U) {
-    const float inv = 1.0f / swk[0];
+    const float inv = 1.0f / tk[0];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const int s = g + NSYS * k;
       if (s < a.nsym) zw[(size_t)s * a.U + i] = user_nu ? zf[k] : make_float2(zf[k].x * inv, zf[k].y * inv);
     }
-    if (g == 0 && a.s2) a.s2[(size_t)w * a.U + i] = user_nu ? svk[0] : inv;
+    if (g == 0 && a.s2) a.s2[(size_t)w * a.U + i] = user_nu ? tk[0] : inv;
   }
   if (lane == 0 && routed_any) enqueue_fp64_sym(a, w);
 }

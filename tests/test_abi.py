@@ -189,19 +189,20 @@ def test_problem_struct_layout():
 @pytest.mark.parametrize("fd", [False, True])
 def test_equalizer_validation(lib, fd):
     call = _call_fd if fd else _call_pd
-    for bad in (-1, 3, 99):
+    for bad in (-1, 4, 99):
         prob, _k = _prob(eqz=bad)
         assert call(lib, prob) == EINVAL
         assert lib.eq_workspace_size(ctypes.byref(prob)) == 0
-    # MRC has no refinement step
-    for prec in (1, 2):
-        prob, _k = _prob(eqz=2, prec=prec)
-        assert call(lib, prob) == ENOTSUP
+    # MRC has no refinement step; the unbiased L-MMSE gain is not refined
+    for eqz in (2, 3):
+        for prec in (1, 2):
+            prob, _k = _prob(eqz=eqz, prec=prec)
+            assert call(lib, prob) == ENOTSUP
     # multi-vector calls take every equaliser, but MRC no refining form
     prob, _k = _prob(eqz=2, prec=1)
     assert _call_sym(lib, prob, 4, fd) == ENOTSUP
-    # the adjoint is L-MMSE only
-    for eqz in (1, 2):
+    # the adjoint is (biased) L-MMSE only
+    for eqz in (1, 2, 3):
         prob, _k = _prob(eqz=eqz)
         assert lib.eq_backward_workspace_size(ctypes.byref(prob)) == 0
         if fd:

@@ -1,5 +1,5 @@
-"""GPU parity of the ZF and MRC equalisers (Section III-A; Section IV-A for
-FD) against the FP64 oracle, element by element on the same seeded inputs:
+"""GPU parity of the ZF, MRC and unbiased L-MMSE equalisers (Section III-A;
+Section IV-A for FD) against the FP64 oracle, element by element on the same seeded inputs:
 max over systems of ||z - z_ref||_inf / ||z_ref||_inf within the form's
 gate, post-equalisation SINR within 0.05 dB.  Plus the degenerate cases:
 noise-free ZF recovery, a user with no channel (MRC) and a rank-deficient
@@ -53,7 +53,7 @@ SHAPES = [  # (W, B, U, C or offsets); every cluster has B_c >= U (ZF FD)
     (5, 130, 24, [0, 60, 130]),
 ]
 CASES = [("zf", p) for p in ("fp32", "bf16x3", "bf16_refine", "bf16x3_refine")] + \
-        [("mrc", p) for p in ("fp32", "bf16x3")]
+        [("mrc", p) for p in ("fp32", "bf16x3")] + [("lmmse_unbiased", p) for p in ("fp32", "bf16x3")]
 
 
 def _batch(shape, seed, snr=10.0):
@@ -80,7 +80,7 @@ def test_linear_matches_oracle(mode, kind, prec, shape):
     assert ((info & ~(1 << 30)) == 0).all()
 
 
-@pytest.mark.parametrize("kind", ["zf", "mrc"])
+@pytest.mark.parametrize("kind", ["zf", "mrc", "lmmse_unbiased"])
 def test_fd_given_weights(kind):
     b = _batch((31, 96, 8, 3), seed=3)
     nu = np.random.default_rng(4).uniform(0.1, 1.0, size=(31, 3, 8))
@@ -136,3 +136,23 @@ def test_zf_rank_deficient_gram():
     assert ((piv == 0) | (piv >= 7)).all(), piv
     assert (piv > 0).any()
     assert np.isnan(z[piv > 0]).all() and np.isnan(s2[piv > 0]).all()
+
+
+@pytest.mark.parametrize("mode", ["pd", "fd"])
+def test_unbiased_is_scaled_lmmse(mode):
+    """PD: the unbiased outputs are the L-MMSE outputs divided by
+    mu = 1 - sigma2 / E_s (both from the GPU); FD: unit-gain local estimates
+    give a fused estimate whose regression on the symbols has slope near 1,
+    where the biased one is below 1."""
+    b = _batch((1000, 256, 16, 8), seed=21, snr=0.0)
+    zu, su = run(mode, "lmmse_unbiased", b, "fp32")
+    zb, sb = run(mode, "lmmse", b, "fp32")
+    if mode == "pd":
+        mu = 1.0 - sb.astype(np.float64)
+        assert max_rel_err(zu, zb / mu) <= 1e-5
+        np.testing.assert_allclose(su, sb / mu, rtol=1e-5)
+    s = b.s
+    slope_u = np.real(np.sum(np.conj(s) * zu) / np.sum(np.abs(s) ** 2))
+    slope_b = np.real(np.sum(np.conj(s) * zb) / np.sum(np.abs(s) ** 2))
+    print(f"{mode}: slope unbiased {slope_u:.4f}, biased {slope_b:.4f}", flush=True)
+    assert abs(slope_u - 1.0) < 0.01 and slope_b < 0.97
