@@ -140,10 +140,11 @@ def _sampled(data, fn, ref, tol, nsample, seed, **kw):
 
 
 @pytest.mark.parametrize("mode", ["pd", "fd"])
-@pytest.mark.parametrize("kind", ["zf", "mrc"])
+@pytest.mark.parametrize("kind", ["zf", "mrc", "lmmse_unbiased"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_linear_equalisers_at_launch_size(c2_full, c3_full, mode, kind, prec):
-    """ZF and MRC at 38,400 (B=256) and 4,800 (B=1024) systems, sampled."""
+    """ZF, MRC and the unbiased L-MMSE at 38,400 (B=256) and 4,800 (B=1024)
+    systems, sampled."""
     from paper_1808_04473_amd import api
     fn = api.eq_pd if mode == "pd" else api.eq_fd
     rf = oracle.eq_pd_linear if mode == "pd" else oracle.eq_fd_linear
