@@ -104,7 +104,7 @@ typedef enum {
                diagonal of the inverse that gives mu.  A user with no
                channel energy in the system (FD: in one cluster) has
                mu_u = 0; its outputs (FD: the fused ones) are then not
-               finite, while info stays 0.
+               finite, and info reports no failure for it.
    The multi-vector calls take every equaliser; the backward calls and the
    ragged plans are L-MMSE only. */
 typedef enum { EQ_LMMSE = 0, EQ_ZF = 1, EQ_MRC = 2, EQ_LMMSE_UNBIASED = 3 } eq_equalizer;
