@@ -207,7 +207,8 @@ def symbol_measurements(Hn, n0, off, H, steps, S, tag):
 
 def extra_measurements(Hn, yn, n0, off, H, y, steps):
     """The other rows of the path, each timed the same way and parity-sampled
-    against the oracle: single-frame latency (W = 1200), the B = 1024 / U = 32
+    against the oracle: single-frame latency (W = 1200), the headline sweep
+    replayed from a HIP graph, the B = 1024 / U = 32
     workload in every precision form, ragged batches of 4096 systems, ZF,
     MRC and LAMA on the headline systems, 14 receive vectors per channel
     matrix, and the FD forward + adjoint of the differentiation workload."""
@@ -220,6 +221,36 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
     H1, y1 = H[:W_FRAME].contiguous(), y[:W_FRAME].contiguous()
     for mode, fn in (("pd", api.eq_pd), ("fd", api.eq_fd)):
         out[f"latency_w{W_FRAME}_{mode}_fp32"] = _timed(lambda: fn(H1, y1, n0, off), steps, 3)
+
+    # one sweep of the headline workload captured in a HIP graph and replayed:
+    # the same launches without the host side of a call; each replay must
+    # reproduce the eager result exactly
+    W, B, U = H.shape
+    for mode, fn in (("pd", api.eq_pd), ("fd", api.eq_fd)):
+        zg = torch.empty((W, U), dtype=torch.complex64, device=dev)
+        sg = torch.empty((W, U), dtype=torch.float32, device=dev)
+        ig = torch.empty((W,) if mode == "pd" else (W, len(off) - 1), dtype=torch.int32, device=dev)
+        prob, _o = api.make_problem(W, B, U, off, n0)
+        wsg = api.workspace(prob, dev)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn(H, y, n0, off, out=(zg, sg, ig), ws=wsg)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(H, y, n0, off, out=(zg, sg, ig), ws=wsg)
+        t = _timed(g.replay, steps, 3)
+        ze, se = fn(H, y, n0, off)
+        torch.cuda.synchronize()
+        t.update({"subcarriers_per_s": W / (t["call_ms_mean"] * 1e-3),
+                  "alg_GBps": W * bytes_per_system() / (t["call_ms_mean"] * 1e-3) / 1e9,
+                  "replay_equals_eager": bool(torch.equal(torch.view_as_real(zg), torch.view_as_real(ze))
+                                              and torch.equal(sg, se))})
+        t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+        out[f"graph_replay_B256_U16_{mode}_fp32"] = t
+        del g
 
     # B = 1024 antennas in 16 clusters of 64, U = 32, 4 frames x 1200 (1.3 GB of H)
     c3 = [synth.config_batch(3, 10.0, frame=f) for f in range(4)]
