@@ -255,3 +255,22 @@ def test_lama_symbols_validation(lib, fd):
     assert call(p2, 4, 2, 16) == ENOTSUP
     p0, _k0 = _prob(W=0)
     assert call(p0, 4, 2, 16) == 0
+
+
+def test_binding_names_match_header_enums():
+    """The binding's precision and equaliser names map to the values that
+    include/dbpeq.h gives the enumerators."""
+    import re
+    from paper_1808_04473_amd import api
+    text = open(HEADER).read()
+
+    def enum(name):
+        body = re.search(r"typedef enum \{([^}]*)\}\s*" + name + ";", text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        return {k: int(v) for k, v in re.findall(r"(EQ_\w+)\s*=\s*(\d+)", body)}
+
+    eqz = enum("eq_equalizer")
+    assert eqz == {"EQ_LMMSE": 0, "EQ_ZF": 1, "EQ_MRC": 2, "EQ_LMMSE_UNBIASED": 3}
+    assert {f"EQ_{k.upper()}": v for k, v in api.EQUALIZERS.items()} == eqz
+    prec = enum("eq_precision")
+    assert {f"EQ_{k.upper()}": v for k, v in api.PRECISIONS.items()} == prec
