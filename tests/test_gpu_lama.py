@@ -71,6 +71,7 @@ def test_lama_fd_given_weights():
     assert max_db_err(s2, sr) <= TOL_DB
 
 
+@pytest.mark.filterwarnings("ignore:invalid value:RuntimeWarning")  # the oracle on the NaN input
 @pytest.mark.parametrize("mode", ["pd", "fd"])
 def test_lama_non_finite_input(mode):
     b = synth.make_batch(8, 64, 8, 2, 10.0, "16qam", seed=32)
