@@ -529,8 +529,8 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["hbm_frac"],
                      "traffic": traffic,
-                     "kernel": "eq_forward_kernel<16, FP32, PD> (+ queue reset and FP64 re-solve "
-                               "launches, included in the timed call)",
+                     "kernel": "eq_forward_kernel<16, FP32, PD> (+ the FP64 re-solve launch, which "
+                               "also clears its queue; included in the timed call)",
                      "alg_bytes_per_launch": launch_bytes,
                      "alg_bytes_per_system": bps,
                      "read_ceiling_GBps": ceiling,
