@@ -103,10 +103,14 @@ def eq_pd_lama(H, y, n0, cluster_off, t_max, order, es=1.0):
     return z, np.repeat(s2[:, None], U, axis=1)
 
 
-def eq_fd_lama(H, y, n0, cluster_off, t_max, order, nu=None, es=1.0):
+def eq_fd_lama(H, y, n0, cluster_off, t_max, order, nu=None, es=1.0, return_clusters=False):
     """LAMA-FD: Algorithm 1 in every cluster on the 1/sqrt(w_c)-normalised
     statistics, fused by eq. (fusionrule) with Lemma 1's weights (or `nu`
-    [W][C][U], used as given); fused variance sum_c nu^2 sigma_c^2."""
+    [W][C][U], used as given); fused variance sum_c nu^2 sigma_c^2.
+
+    With return_clusters=True also returns the local estimates z_c [W][C][U],
+    their variances sigma2_c [W][C] and, per cluster, Algorithm 1's trace
+    (a list over iterations of (z_c^t [W][U], sigma2_c^t [W]))."""
     Gc, mc = local_statistics(H, y, cluster_off)
     W, B, U = np.asarray(H).shape
     off = [int(v) for v in cluster_off]
@@ -114,14 +118,20 @@ def eq_fd_lama(H, y, n0, cluster_off, t_max, order, nu=None, es=1.0):
     pts = qam_points(order, es)
     z_c = np.empty((W, C, U), np.complex128)
     s2_c = np.empty((W, C, U), np.float64)
+    traces = []
     for c in range(C):
         wc = (off[c + 1] - off[c]) / B
-        z, s2 = lama_pd(Gc[:, c] / wc, mc[:, c] / wc, float(n0) / wc, (U / B) / wc, t_max, pts)
+        z, s2, tr = lama_pd(Gc[:, c] / wc, mc[:, c] / wc, float(n0) / wc, (U / B) / wc, t_max, pts,
+                            return_trace=True)
         z_c[:, c] = z
         s2_c[:, c] = s2[:, None]
+        traces.append(tr)
     if nu is None:
         p = 1.0 / s2_c
         w = p / p.sum(axis=1, keepdims=True)
     else:
         w = np.asarray(nu, np.float64)
-    return np.sum(w * z_c, axis=1), np.sum(w * w * s2_c, axis=1)
+    z, s2 = np.sum(w * z_c, axis=1), np.sum(w * w * s2_c, axis=1)
+    if return_clusters:
+        return z, s2, z_c, s2_c[:, :, 0], traces
+    return z, s2

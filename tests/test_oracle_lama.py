@@ -1,7 +1,9 @@
-"""Pins of the LAMA oracle (Algorithm 1, eq. (F), Theorem 1, Lemma 2):
+"""Pins of the LAMA oracle (Algorithm 1, eq. (F), Theorem 1, Lemma 2, Theorem 3):
 the QPSK posterior mean in closed form, the denoiser's limits, the original
 H-domain LAMA of the derivation of Algorithm 1, the first iteration, FD with
-one cluster, and the state evolution of Theorem 1 on a large system."""
+one cluster, the state evolution of Theorem 1 on a large system, and LAMA-FD
+with several clusters against the normalised cluster systems of the proof of
+Lemma 2 and their per-cluster state evolution."""
 import numpy as np
 import pytest
 
@@ -117,3 +119,74 @@ def test_state_evolution_tracks_lama_pd():
         emp = np.mean(np.abs(z - s) ** 2)
         assert abs(np.mean(s2) / se[t] - 1) < 0.05, (t, np.mean(s2), se[t])
         assert abs(emp / se[t] - 1) < 0.08, (t, emp, se[t])
+
+
+# ---- LAMA-FD with several clusters: the per-cluster normalisation of the
+#      proof of Lemma 2, pinned against the H-domain LAMA and Theorem 1.
+
+def _large_system(rng, order, n0, W=40, B=512, U=64):
+    pts = oracle.qam_points(order)
+    H = _h(rng, W, B, U)
+    s = pts[rng.integers(0, order, (W, U))]
+    y = (H @ s[..., None])[..., 0] + np.sqrt(n0 / 2) * (rng.standard_normal((W, B)) + 1j * rng.standard_normal((W, B)))
+    return H, y, s, pts
+
+
+FD_PARTITIONS = {"C2_w_quarter_three_quarters": [0, 128, 512], "C4_uniform": [0, 128, 256, 384, 512]}
+
+
+@pytest.mark.parametrize("order", [4, 16])
+@pytest.mark.parametrize("part", list(FD_PARTITIONS))
+def test_fd_lama_clusters_equal_lama_on_normalised_cluster_systems(order, part):
+    """Each cluster's LAMA is the original H-domain LAMA (pinned to Algorithm 1
+    above) run on the cluster's own system scaled by 1/sqrt(w_c): channel
+    H_c / sqrt(w_c) (entries of variance 1/B_c, so that its system ratio is
+    U/B_c), receive vector y_c / sqrt(w_c) and noise variance N0 / w_c (proof
+    of Lemma 2).  The normalised system is built here from H and y directly,
+    not from the oracle's scaled statistics, so a mis-scaled N0 or beta in the
+    oracle's cluster iteration fails this test."""
+    off = FD_PARTITIONS[part]
+    rng = np.random.default_rng(7)
+    n0 = 0.1 if order == 4 else 0.02
+    H, y, _, pts = _large_system(rng, order, n0, W=8)
+    B = H.shape[1]
+    T = 5
+    _, _, z_c, s2_c, _ = oracle.eq_fd_lama(H, y, n0, off, T, order, return_clusters=True)
+    for c in range(len(off) - 1):
+        wc = (off[c + 1] - off[c]) / B
+        Hc = H[:, off[c]:off[c + 1]] / np.sqrt(wc)
+        yc = y[:, off[c]:off[c + 1]] / np.sqrt(wc)
+        z_ref, s2_ref = oracle.lama_original(Hc, yc, n0 / wc, T, pts)
+        np.testing.assert_allclose(z_c[:, c], z_ref, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(s2_c[:, c], s2_ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("order", [4, 16])
+@pytest.mark.parametrize("part", list(FD_PARTITIONS))
+def test_fd_lama_state_evolution_per_cluster(order, part):
+    """Theorem 1 applied to cluster c of the normalised relation (proof of
+    Lemma 2): the variance that cluster's iteration carries, N0/w_c +
+    (beta/w_c) phi_c^t, and the empirical MSE of its estimate z_c^t follow
+    sigma_{c,1}^2 = (N0 + beta E_s)/w_c, sigma_{c,t+1}^2 = (N0 + beta
+    Psi(sigma_{c,t}^2))/w_c, within 5% / 8% (B = 512, U = 64; w = (1/4, 3/4)
+    and four equal clusters).  The fused variance is (sum_c 1/sigma_c^2)^{-1}
+    (Theorem 3), and the empirical MSE of the fused estimate follows it."""
+    off = FD_PARTITIONS[part]
+    rng = np.random.default_rng(7)
+    n0 = 0.1 if order == 4 else 0.02
+    H, y, s, pts = _large_system(rng, order, n0)
+    W, B, U = H.shape
+    beta, T = U / B, 5
+    z, s2, _, s2_c, traces = oracle.eq_fd_lama(H, y, n0, off, T, order, return_clusters=True)
+    for c in range(len(off) - 1):
+        wc = (off[c + 1] - off[c]) / B
+        se = [(n0 + beta * 1.0) / wc]
+        for _ in range(T - 1):
+            se.append((n0 + beta * _psi(se[-1], pts, rng)) / wc)
+        for t, (zt, st) in enumerate(traces[c]):
+            emp = np.mean(np.abs(zt - s) ** 2)
+            assert abs(np.mean(st) / se[t] - 1) < 0.05, (c, t, np.mean(st), se[t])
+            assert abs(emp / se[t] - 1) < 0.08, (c, t, emp, se[t])
+    fused = 1.0 / np.sum(1.0 / s2_c, axis=1)
+    np.testing.assert_allclose(s2, np.repeat(fused[:, None], U, axis=1), rtol=1e-12)
+    assert abs(np.mean(np.abs(z - s) ** 2) / np.mean(fused) - 1) < 0.08
