@@ -28,7 +28,6 @@ sys.path.insert(0, ROOT)
 
 B, C, U, W_FRAME, SNR_DB = 256, 8, 16, 1200, 10.0
 HBM_PEAK_GBS = 8000.0
-CPU_SAMPLE_DEFAULT = 38400
 CPU_MIN_SECONDS = 10.0
 
 
@@ -75,22 +74,113 @@ def make_inputs(frames):
     return np.concatenate(Hs), np.concatenate(ys), n0, off
 
 
-def cpu_baseline(H, y, n0, off, nsys, min_seconds=CPU_MIN_SECONDS, max_passes=8):
-    """The FP64 oracle (as it stands) on the first `nsys` systems of the step,
-    repeated until about `min_seconds` of wall time have passed."""
+def cpu_cores():
+    """Host threads the oracle baseline may use: the CPUs this process may run
+    on, capped at 16 (the host share of one GPU) or at OMP_NUM_THREADS when set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = 16
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        cap = min(cap, int(env))
+    return max(1, min(n, cap))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_worker_init():
+    # one BLAS / OpenMP thread per worker process: the parallelism is the pool
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _cpu_worker(task):
+    """Generates its frames of the step (not timed), then runs the FP64 PD
+    oracle over them, frame by frame, until `seconds` of wall time have passed."""
+    frames, seconds = task
     import oracle
-    passes = 0
-    t0, c0 = time.perf_counter(), time.process_time()
-    while passes < max_passes:
-        oracle.eq_pd(H[:nsys], y[:nsys], n0, off)
-        passes += 1
-        if time.perf_counter() - t0 >= min_seconds:
+    from paper_1808_04473_amd import synth
+    batches = [synth.config_batch(2, SNR_DB, frame=f) for f in frames]
+    n, t0, c0 = 0, time.time(), time.process_time()
+    while True:
+        for b in batches:
+            oracle.eq_pd(b.H, b.y, b.n0, b.cluster_off)
+            n += b.H.shape[0]
+        if time.time() - t0 >= seconds:
             break
-    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
-    return {"value": passes * nsys / wall, "unit": "subcarriers/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": f"PD L-MMSE (complex128 numpy oracle) over the first {nsys} of the step's "
-                      f"systems, {passes} passes, {wall:.1f} s wall, {cpu:.1f} s CPU"}
+    return n, t0, time.time(), time.process_time() - c0
+
+
+class CpuBaseline:
+    """The FP64 oracle (as it stands) on the host cores, one process per core.
+
+    The pool is forked before anything touches the GPU; each worker equalises
+    its share of the step's frames (generated from the same seeds as the GPU
+    inputs) repeatedly for about `seconds` of wall time.  Throughput is the
+    systems done over the span from the first worker's start to the last
+    worker's end."""
+
+    def __init__(self, frames, seconds=CPU_MIN_SECONDS, cores=None):
+        import multiprocessing as mp
+        self.cores = cores or cpu_cores()
+        self.frames = frames
+        self.seconds = seconds
+        self.pool = mp.get_context("fork").Pool(self.cores, initializer=_cpu_worker_init)
+
+    def run(self):
+        shares = [list(range(k, self.frames, self.cores)) for k in range(self.cores)]
+        shares = [sh for sh in shares if sh]
+        try:
+            res = self.pool.map(_cpu_worker, [(sh, self.seconds) for sh in shares])
+        finally:
+            self.pool.close()
+            self.pool.join()
+        n = sum(r[0] for r in res)
+        span = max(r[2] for r in res) - min(r[1] for r in res)
+        cpu = sum(r[3] for r in res)
+        return {"value": n / span, "unit": "subcarriers/s", "cores": len(shares), "kind": "oracle",
+                "cpu_model": cpu_model(),
+                "sample": f"PD L-MMSE, complex128 NumPy oracle, {len(shares)} worker processes with one "
+                          f"thread each over the step's {self.frames} frames x {W_FRAME} subcarriers "
+                          f"(B={B}, C={C}, U={U}), each worker repeating its frames for about "
+                          f"{self.seconds:g} s: {n} systems in {span:.1f} s wall, {cpu:.1f} s CPU"}
+
+    def close(self):
+        self.pool.terminate()
+        self.pool.join()
+
+
+COMPACT_VARIANT_KEYS = ("call_ms_mean", "hbm_frac", "parity_max_rel_err_z")
+
+
+def compact_record(out, full_path=None):
+    """The driver-facing last line: the headline, its roofline and the CPU
+    baseline, the BF16-MFMA comparison and one short entry per timed form
+    (the full record, with every other workload, goes to `full_path`)."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+            "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline",
+            "bf16_mfma_vs_fp32")
+    rec = {k: out[k] for k in keys if k in out}
+    rec["forms"] = {k: {kk: (round(v[kk], 7) if isinstance(v.get(kk), float) else v.get(kk))
+                        for kk in COMPACT_VARIANT_KEYS if kk in v}
+                    for k, v in out.get("variants", {}).items()}
+    if full_path:
+        rec["full_record"] = os.path.relpath(full_path, ROOT) if full_path.startswith(ROOT) else full_path
+    return rec
 
 
 VARIANTS = [("pd", "fp32"), ("pd", "bf16x3"), ("pd", "bf16_refine"), ("pd", "bf16x3_refine"),
@@ -404,7 +494,12 @@ def main(argv=None):
     ap.add_argument("--frames", type=int, default=32)
     ap.add_argument("--variants", default="all",
                     help="comma list of mode:prec (e.g. pd:fp32,fd:bf16x3_refine) or 'all'")
-    ap.add_argument("--cpu-sample", type=int, default=CPU_SAMPLE_DEFAULT)
+    ap.add_argument("--cpu-seconds", type=float, default=CPU_MIN_SECONDS,
+                    help="wall time of each oracle worker process in the CPU baseline")
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="oracle worker processes (default: the host CPUs, at most 16)")
+    ap.add_argument("--full-out", default=os.path.join(ROOT, "gpurun_out", "bench_full.json"),
+                    help="where the full record (every workload) is written; '' = nowhere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -421,6 +516,18 @@ def main(argv=None):
               "and this build has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
         return 2
 
+    # the oracle's worker processes are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and args.nsym == 1:
+        cpu = CpuBaseline(args.frames, args.cpu_seconds, args.cpu_cores or None)
+    try:
+        return _gpu_main(args, cpu)
+    finally:
+        if cpu is not None:
+            cpu.close()
+
+
+def _gpu_main(args, cpu):
     import torch
     from paper_1808_04473_amd import api
     api.load_library()
@@ -549,9 +656,19 @@ def main(argv=None):
                 "fp32_parity_max_rel_err_z": b.get("parity_max_rel_err_z")}
     if not args.no_extras:
         out["other_workloads"] = extra_measurements(Hn, yn, n0, off, H, y, min(args.steps, 20))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(Hn, yn, n0, off, min(args.cpu_sample, W))
-    print(json.dumps(out), flush=True)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu.run()
+    full_path = args.full_out or None
+    if full_path:
+        try:
+            os.makedirs(os.path.dirname(full_path), exist_ok=True)
+            with open(full_path, "w") as f:
+                json.dump(out, f, indent=1)
+            print(f"# full record: {full_path}", file=sys.stderr, flush=True)
+        except OSError as e:
+            print(f"# full record not written ({e})", file=sys.stderr, flush=True)
+            full_path = None
+    print(json.dumps(compact_record(out, full_path)), flush=True)
     return 0
 
 

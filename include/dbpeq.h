@@ -69,7 +69,11 @@ typedef enum {
   /* Gram + matched filter in FP32 (Gram on FP32 MFMA), FP32 solves. */
   EQ_FP32 = 0,
   /* Gram on BF16 MFMA with FP32 accumulation, FP32 matched filter and solves,
-     then one refinement step with the FP32 residual y - H z. */
+     then one refinement step with the FP32 residual y - H z.  PD only: FD
+     (eq_fd and FD plans) returns EQ_ENOTSUP, because its fusion weights come
+     from the diagonal of the inverse of G_c + rho I, which the refinement
+     step does not correct and the single-BF16 Gram leaves about 1e-3 off; FD uses
+     EQ_BF16X3_REFINE, whose split-BF16 Gram gives them to FP32 accuracy. */
   EQ_BF16_REFINE = 1,
   /* As EQ_BF16_REFINE with each operand split into a BF16 high and low part
      (three BF16 products hi*hi + hi*lo + lo*hi per Gram term). */

@@ -132,9 +132,62 @@ def _check_inputs(H, y):
         raise ValueError("H and y must be on a HIP device (no CPU fallback)")
     if H.dtype != torch.complex64 or y.dtype != torch.complex64:
         raise TypeError("H and y must be complex64")
+    if H.device != y.device:
+        raise ValueError("H and y must be on the same device")
     if H.dim() != 3 or y.dim() != 2 or H.shape[0] != y.shape[0] or H.shape[1] != y.shape[1]:
         raise ValueError(f"shapes H {tuple(H.shape)} / y {tuple(y.shape)} are not [W][B][U] / [W][B]")
     return H.contiguous(), y.contiguous()
+
+
+def _check_tensor(name, t, shape, dtype, device):
+    """A caller-supplied output or weight tensor: its pointer goes to the
+    kernels, which trust its extent, so it must match exactly."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, not {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, not {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _outputs(out, zshape, s2shape, infoshape, device):
+    """Output tensors: allocated here, or the caller's (z, sigma2, info)
+    checked against the shapes the call writes (sigma2 and info may be None)."""
+    if out is None:
+        return (torch.empty(zshape, dtype=torch.complex64, device=device),
+                torch.empty(s2shape, dtype=torch.float32, device=device),
+                torch.empty(infoshape, dtype=torch.int32, device=device))
+    if not isinstance(out, (tuple, list)) or len(out) != 3:
+        raise ValueError("out must be a tuple (z, sigma2, info)")
+    z, s2, info = out
+    _check_tensor("out z", z, zshape, torch.complex64, device)
+    if s2 is not None:
+        _check_tensor("out sigma2", s2, s2shape, torch.float32, device)
+    if info is not None:
+        _check_tensor("out info", info, infoshape, torch.int32, device)
+    return z, s2, info
+
+
+def _check_nu(nu, W, C, U, device):
+    if nu is None:
+        return None
+    if not isinstance(nu, torch.Tensor) or nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) \
+            or nu.device != device:
+        raise ValueError("nu must be float32 [W][C][U] on the same device")
+    return nu.contiguous()
+
+
+def _check_ws(ws, device):
+    if ws is None:
+        return None
+    if not isinstance(ws, torch.Tensor) or ws.device != device or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 tensor on the same device")
+    return ws
 
 
 def workspace(prob: EqProblem, device) -> torch.Tensor:
@@ -171,13 +224,8 @@ def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, ou
     H, y = _check_inputs(H, y)
     W, B, U = H.shape
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
-    if out is None:
-        z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
-        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
-        info = torch.empty((W,), dtype=torch.int32, device=H.device)
-    else:
-        z, s2, info = out
-    ws = _cached_workspace(prob, H.device) if ws is None else ws
+    z, s2, info = _outputs(out, (W, U), (W, U), (W,), H.device)
+    ws = _cached_workspace(prob, H.device) if ws is None else _check_ws(ws, H.device)
     st = lib.eq_pd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_pd", st)
@@ -193,17 +241,9 @@ def eq_fd(H, y, n0, cluster_off, nu=None, precision="fp32", es=1.0, return_info=
     W, B, U = H.shape
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
     C = prob.C
-    if nu is not None:
-        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
-            raise ValueError("nu must be float32 [W][C][U] on the same device")
-        nu = nu.contiguous()
-    if out is None:
-        z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
-        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
-        info = torch.empty((W, C), dtype=torch.int32, device=H.device)
-    else:
-        z, s2, info = out
-    ws = _cached_workspace(prob, H.device) if ws is None else ws
+    nu = _check_nu(nu, W, C, U, H.device)
+    z, s2, info = _outputs(out, (W, U), (W, U), (W, C), H.device)
+    ws = _cached_workspace(prob, H.device) if ws is None else _check_ws(ws, H.device)
     st = lib.eq_fd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(nu), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_fd", st)
@@ -217,6 +257,8 @@ def _check_sym_inputs(H, Y):
         raise ValueError("H and Y must be on a HIP device (no CPU fallback)")
     if H.dtype != torch.complex64 or Y.dtype != torch.complex64:
         raise TypeError("H and Y must be complex64")
+    if H.device != Y.device:
+        raise ValueError("H and Y must be on the same device")
     if H.dim() != 3 or Y.dim() != 3 or H.shape[0] != Y.shape[0] or H.shape[1] != Y.shape[2]:
         raise ValueError(f"shapes H {tuple(H.shape)} / Y {tuple(Y.shape)} are not [W][B][U] / [W][S][B]")
     return H.contiguous(), Y.contiguous()
@@ -229,19 +271,11 @@ def _sym_call(fd, H, Y, n0, cluster_off, nu, precision, es, return_info, out, ws
     S = Y.shape[1]
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
     C = prob.C
-    if nu is not None:
-        if not fd:
-            raise ValueError("nu applies to FD only")
-        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
-            raise ValueError("nu must be float32 [W][C][U] on the same device")
-        nu = nu.contiguous()
-    if out is None:
-        z = torch.empty((W, S, U), dtype=torch.complex64, device=H.device)
-        s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
-        info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
-    else:
-        z, s2, info = out
-    ws = _cached_workspace(prob, H.device) if ws is None else ws
+    if nu is not None and not fd:
+        raise ValueError("nu applies to FD only")
+    nu = _check_nu(nu, W, C, U, H.device)
+    z, s2, info = _outputs(out, (W, S, U), (W, U), (W, C) if fd else (W,), H.device)
+    ws = _cached_workspace(prob, H.device) if ws is None else _check_ws(ws, H.device)
     if fd:
         st = lib.eq_fd_sym(ctypes.byref(prob), S, _ptr(H), _ptr(Y), _ptr(nu), _ptr(z), _ptr(s2),
                            _ptr(info), _ptr(ws), ws.numel(), _stream())
@@ -271,12 +305,9 @@ def _lama_call(fd, H, y, n0, cluster_off, t_max, qam, nu, precision, es, return_
     W, B, U = H.shape
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
     C = prob.C
-    if nu is not None:
-        if not fd:
-            raise ValueError("nu applies to FD only")
-        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
-            raise ValueError("nu must be float32 [W][C][U] on the same device")
-        nu = nu.contiguous()
+    if nu is not None and not fd:
+        raise ValueError("nu applies to FD only")
+    nu = _check_nu(nu, W, C, U, H.device)
     z = torch.empty((W, U), dtype=torch.complex64, device=H.device)
     s2 = torch.empty((W, U), dtype=torch.float32, device=H.device)
     info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
@@ -309,12 +340,9 @@ def _lama_sym_call(fd, H, Y, n0, cluster_off, t_max, qam, nu, precision, es, ret
     S = Y.shape[1]
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision)
     C = prob.C
-    if nu is not None:
-        if not fd:
-            raise ValueError("nu applies to FD only")
-        if nu.dtype != torch.float32 or tuple(nu.shape) != (W, C, U) or nu.device != H.device:
-            raise ValueError("nu must be float32 [W][C][U] on the same device")
-        nu = nu.contiguous()
+    if nu is not None and not fd:
+        raise ValueError("nu applies to FD only")
+    nu = _check_nu(nu, W, C, U, H.device)
     z = torch.empty((W, S, U), dtype=torch.complex64, device=H.device)
     s2 = torch.empty((W, S, U), dtype=torch.float32, device=H.device)
     info = torch.empty((W, C) if fd else (W,), dtype=torch.int32, device=H.device)
@@ -381,10 +409,8 @@ def eq_fd_backward(H, y, n0, cluster_off, gz=None, gs=None, nu=None, es=1.0):
     W, B, U = H.shape
     prob, _off = make_problem(W, B, U, cluster_off, n0, es, "fp32")
     gz, gs = _grad_inputs(gz, gs, W, U, H.device)
-    gnu = None
-    if nu is not None:
-        nu = nu.contiguous()
-        gnu = torch.empty_like(nu)
+    nu = _check_nu(nu, W, prob.C, U, H.device)
+    gnu = None if nu is None else torch.empty_like(nu)
     gH = torch.empty_like(H)
     gy = torch.empty_like(y)
     gn0 = torch.zeros((), dtype=torch.float32, device=H.device)
@@ -421,7 +447,11 @@ class Plan:
         _check("eq_plan_create", st)
         self._h = h
         self._lib = lib
-        self.nz = int(max(np.asarray(z_off, np.int64) + np.asarray(U, np.int64)))
+        Bn, Un = np.asarray(B, np.int64), np.asarray(U, np.int64)
+        # elements of each pool that the descriptors address
+        self.nh = int(max(np.asarray(h_off, np.int64) + Bn * Un)) if n else 0
+        self.ny = int(max(np.asarray(y_off, np.int64) + Bn)) if n else 0
+        self.nz = int(max(np.asarray(z_off, np.int64) + Un)) if n else 0
 
     @classmethod
     def from_ragged(cls, rb, fd=False, precision="fp32", tune_cache=None):
@@ -429,15 +459,33 @@ class Plan:
                    rb.cluster_sizes, fd=fd, precision=precision, es=rb.es, tune_cache=tune_cache)
 
     def execute(self, Hpool, ypool, out=None):
-        for t in (Hpool, ypool):
-            if t.device.type != "cuda" or t.dtype != torch.complex64 or not t.is_contiguous():
-                raise ValueError("pools must be contiguous complex64 device tensors")
+        """Equalises every system: (z pool, sigma2 pool, info [nsys]).  The
+        pools must cover every descriptor's extent (checked here: the kernels
+        trust the offsets)."""
+        for name, t, need in (("Hpool", Hpool, self.nh), ("ypool", ypool, self.ny)):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64 \
+                    or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError(f"{name} must be a contiguous 1-D complex64 device tensor")
+            if t.numel() < need:
+                raise ValueError(f"{name} holds {t.numel()} elements; the descriptors address {need}")
+        if ypool.device != Hpool.device:
+            raise ValueError("Hpool and ypool must be on the same device")
         if out is None:
             z = torch.empty(self.nz, dtype=torch.complex64, device=Hpool.device)
             s2 = torch.empty(self.nz, dtype=torch.float32, device=Hpool.device)
             info = torch.empty(self.nsys, dtype=torch.int32, device=Hpool.device)
         else:
+            if not isinstance(out, (tuple, list)) or len(out) != 3:
+                raise ValueError("out must be a tuple (z, sigma2, info)")
             z, s2, info = out
+            for name, t, dt, need in (("out z", z, torch.complex64, self.nz), ("out sigma2", s2, torch.float32, self.nz),
+                                      ("out info", info, torch.int32, self.nsys)):
+                if t is None and name != "out z":
+                    continue
+                if not isinstance(t, torch.Tensor) or t.device != Hpool.device or t.dtype != dt \
+                        or not t.is_contiguous() or t.numel() < need:
+                    raise ValueError(f"{name} must be a contiguous {dt} tensor of at least {need} elements "
+                                     f"on {Hpool.device}")
         st = self._lib.eq_plan_execute(self._h, _ptr(Hpool), _ptr(ypool), _ptr(z), _ptr(s2), _ptr(info),
                                        _stream())
         _check("eq_plan_execute", st)

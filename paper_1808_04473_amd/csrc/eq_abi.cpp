@@ -67,6 +67,10 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
                   eq_c32 *z, float *s2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
   eq_status st = check_problem(p);
   if (st != EQ_OK) return st;
+  // FD fuses with weights from diag(A_c^{-1}) of the local Grams; a refinement
+  // step corrects z_c but not that diagonal, which the single-BF16 Gram leaves
+  // about 1e-3 off (the split-BF16 form EQ_BF16X3_REFINE is the FD form)
+  if (fd && p->precision == EQ_BF16_REFINE) return EQ_ENOTSUP;
   if (p->W == 0) return EQ_OK;
   if (!H || !y || !z) return EQ_EINVAL;
   if (!aligned(H, 8) || !aligned(y, 8) || !aligned(z, 8)) return EQ_EINVAL;

@@ -258,7 +258,9 @@ template <int UT, bool FD>
 static hipError_t launch_prec(const FwdArgs &a, int prec, hipStream_t s) {
   switch (prec) {
     case PREC_FP32: return launch_one<UT, PREC_FP32, FD>(a, s);
-    case PREC_BF16: return launch_one<UT, PREC_BF16, FD>(a, s);
+    case PREC_BF16:  // PD only (eq_fd refuses the single-BF16 Gram)
+      if constexpr (FD) return hipErrorInvalidValue;
+      else return launch_one<UT, PREC_BF16, FD>(a, s);
     case PREC_BF16X3: return launch_one<UT, PREC_BF16X3, FD>(a, s);
     default: return launch_one<UT, PREC_BF16X3_NR, FD>(a, s);
   }

@@ -264,6 +264,9 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const 
   if (nsys < 1 || !desc || !sizes || nsizes < 1) return EQ_EINVAL;
   if (fd != 0 && fd != 1) return EQ_EINVAL;
   if (precision < EQ_FP32 || precision > EQ_BF16X3) return EQ_EINVAL;
+  // FD fuses with weights from diag(A_c^{-1}), which the refinement step does
+  // not correct: the single-BF16 Gram leaves them about 1e-3 off
+  if (fd && precision == EQ_BF16_REFINE) return EQ_ENOTSUP;
   if (!isfinite(es) || !(es > 0.f)) return EQ_EINVAL;
   eq_plan *p = new eq_plan();
   p->fd = fd;

@@ -172,7 +172,10 @@ hipError_t launch_ragged(const RaggedArgs &a, bool fd, int prec, int grid, hipSt
   else hipLaunchKernelGGL((eq_ragged_kernel<P, false>), g, b, 0, s, a);
   switch (prec) {
     case PREC_FP32: EQ_RAGGED_LAUNCH(PREC_FP32) break;
-    case PREC_BF16: EQ_RAGGED_LAUNCH(PREC_BF16) break;
+    case PREC_BF16:  // PD only (the plan refuses FD with the single-BF16 Gram)
+      if (fd) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((eq_ragged_kernel<PREC_BF16, false>), g, b, 0, s, a);
+      break;
     case PREC_BF16X3: EQ_RAGGED_LAUNCH(PREC_BF16X3) break;
     default: EQ_RAGGED_LAUNCH(PREC_BF16X3_NR) break;
   }

@@ -42,3 +42,18 @@ def sinr_db_empirical(z, s):
 # gates (error on the equalised symbols; SINR)
 TOL_Z = {"fp32": 1e-4, "bf16_refine": 2e-4, "bf16x3_refine": 2e-4, "bf16x3": 1e-4}
 TOL_DB = 0.05
+
+
+def refused(mode, prec):
+    """Forms the library refuses with EQ_ENOTSUP: FD with the single-BF16
+    Gram (its fusion weights come from diag((G_c + rho I)^{-1}), which the
+    refinement step does not correct)."""
+    return mode == "fd" and prec == "bf16_refine"
+
+
+def expect_refused(fn):
+    """Calls fn() and checks that the library refuses it with EQ_ENOTSUP."""
+    from paper_1808_04473_amd import api
+    with pytest.raises(api.EqError) as e:
+        fn()
+    assert e.value.status == -2, e.value.status

@@ -274,3 +274,57 @@ def test_binding_names_match_header_enums():
     assert {f"EQ_{k.upper()}": v for k, v in api.EQUALIZERS.items()} == eqz
     prec = enum("eq_precision")
     assert {f"EQ_{k.upper()}": v for k, v in api.PRECISIONS.items()} == prec
+
+
+def test_fd_single_bf16_refinement_refused(lib):
+    """FD's fusion weights come from diag((G_c + rho I)^{-1}), which the
+    refinement step does not correct: eq_fd and FD plans refuse the
+    single-BF16 Gram (EQ_ENOTSUP, before any HIP call); PD accepts it."""
+    import ctypes as ct
+    prob, _off = api.make_problem(4, 8, 2, [0, 4, 8], 0.1, 1.0, "bf16_refine")
+    ws = 1 << 12
+    assert lib.eq_fd(ct.byref(prob), A, A, None, A, A, A, A, ws, None) == ENOTSUP
+    for eqz in (0, 1):  # L-MMSE and ZF
+        prob.equalizer = eqz
+        assert lib.eq_fd(ct.byref(prob), A, A, None, A, A, A, A, ws, None) == ENOTSUP
+    # PD with the same problem gets past validation to the workspace check
+    prob.equalizer = 0
+    assert lib.eq_pd(ct.byref(prob), A, A, A, A, A, None, 0, None) == EWORKSPACE
+    desc = (api.EqSys * 1)()
+    desc[0] = api.EqSys(0, 0, 0, 8, 2, 2, 0, 0.1, 0)
+    sizes = np.array([4, 4], np.int32)
+    h = ct.c_void_p()
+    assert lib.eq_plan_create(ct.byref(h), desc, 1, sizes.ctypes.data_as(ct.POINTER(ct.c_int32)), 2, 1, 1,
+                              1.0, None) == ENOTSUP
+    assert not h.value
+
+
+def test_binding_checks_caller_outputs():
+    """Caller-supplied out / nu / ws tensors reach the kernels as raw
+    pointers, so the binding checks shape, dtype, device and contiguity."""
+    import torch
+    cpu = torch.device("cpu")
+    W, U, C = 5, 3, 2
+    z = torch.empty((W, U), dtype=torch.complex64)
+    s2 = torch.empty((W, U), dtype=torch.float32)
+    info = torch.empty((W,), dtype=torch.int32)
+    assert api._outputs((z, s2, info), (W, U), (W, U), (W,), cpu)[0] is z
+    assert api._outputs((z, None, None), (W, U), (W, U), (W,), cpu)[1] is None
+    with pytest.raises(ValueError):
+        api._outputs((z[:4], s2, info), (W, U), (W, U), (W,), cpu)            # too few systems
+    with pytest.raises(ValueError):
+        api._outputs((z, s2, torch.empty((W, C), dtype=torch.int32)), (W, U), (W, U), (W,), cpu)
+    with pytest.raises(TypeError):
+        api._outputs((z, s2.double(), info), (W, U), (W, U), (W,), cpu)
+    with pytest.raises(ValueError):
+        api._outputs((torch.empty((U, W), dtype=torch.complex64).t(), s2, info), (W, U), (W, U), (W,), cpu)
+    with pytest.raises(ValueError):
+        api._outputs((z, s2), (W, U), (W, U), (W,), cpu)
+    meta = torch.device("meta")
+    with pytest.raises(ValueError):
+        api._outputs((z, s2, info), (W, U), (W, U), (W,), meta)               # wrong device
+    with pytest.raises(ValueError):
+        api._check_nu(torch.empty((W, C, U + 1)), W, C, U, cpu)
+    assert api._check_nu(None, W, C, U, cpu) is None
+    with pytest.raises(ValueError):
+        api._check_ws(torch.empty(64, dtype=torch.float32), cpu)

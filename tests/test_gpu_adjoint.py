@@ -153,3 +153,77 @@ def test_pd_autograd_sigma2_loss():
     assert nrel(host(H.grad), rH) <= TOL
     assert nrel(host(y.grad), ry) <= TOL
     assert abs(float(n0.grad) - rn0) <= TOL * abs(rn0)
+
+
+def _config5_user_weights(W, C, U, seed=13):
+    """Weights near the uniform 1/C, perturbed per (w, c, u), given by the user
+    (not renormalised), so the loss depends on each of them (Lemma 1's fusion
+    rule with given weights)."""
+    rng = np.random.default_rng(seed)
+    return ((1.0 + 0.3 * rng.uniform(-1, 1, size=(W, C, U))) / C).astype(np.float32)
+
+
+def test_config5_user_weights_autograd_vs_oracle():
+    """FD at the full config-5 shape (B=256, C=8 x 32, U=16, W=1200) with user
+    fusion weights nu and an MSE loss on the 16-QAM symbols: dL/dH, dL/dy,
+    dL/dN0 and dL/dnu through EqFD.backward vs the oracle's analytic adjoint."""
+    from paper_1808_04473_amd.autograd import eq_fd
+    b = _config5()
+    W, B, U = b.H.shape
+    C = len(b.cluster_off) - 1
+    nun = _config5_user_weights(W, C, U)
+    H = dev(b.H).requires_grad_(True)
+    y = dev(b.y).requires_grad_(True)
+    nu = dev(nun).requires_grad_(True)
+    n0 = torch.tensor(b.n0, dtype=torch.float32, requires_grad=True)
+    z, _ = eq_fd(H, y, n0, b.cluster_off, nu=nu)
+    loss = torch.mean(torch.abs(z - dev(b.s)) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    zr, _ = oracle.eq_fd(b.H, b.y, b.n0, b.cluster_off, nu=nun)
+    gz = 2.0 * (zr - b.s.astype(np.complex128)) / zr.size
+    rH, ry, rn0, rnu = oracle.fd_backward(b.H, b.y, b.n0, b.cluster_off, gz, nu=nun)
+    eH, ey, enu = nrel(host(H.grad), rH), nrel(host(y.grad), ry), nrel(host(nu.grad), rnu)
+    en0 = abs(float(n0.grad) - rn0) / abs(rn0)
+    print(f"config5 user nu: H {eH:.1e} y {ey:.1e} N0 {en0:.1e} nu {enu:.1e}", flush=True)
+    assert eH <= TOL and ey <= TOL and en0 <= TOL and enu <= TOL
+
+
+def test_config5_user_weights_directional_fp64_finite_difference():
+    """Directional derivative of the MSE loss along a random direction in
+    (H, y, N0, nu) on a 16-subcarrier slice of config 5 with user weights:
+    GPU adjoint vs FP64 central differences (step 1e-6) of the oracle."""
+    from paper_1808_04473_amd.autograd import eq_fd
+    b = _config5()
+    W = 16
+    _, B, U = b.H.shape
+    C = len(b.cluster_off) - 1
+    Hn, yn, sn = b.H[:W], b.y[:W], b.s[:W].astype(np.complex128)
+    nun = _config5_user_weights(W, C, U, seed=17)
+    H = dev(Hn).requires_grad_(True)
+    y = dev(yn).requires_grad_(True)
+    nu = dev(nun).requires_grad_(True)
+    n0 = torch.tensor(b.n0, dtype=torch.float32, requires_grad=True)
+    z, _ = eq_fd(H, y, n0, b.cluster_off, nu=nu)
+    loss = torch.mean(torch.abs(z - dev(b.s[:W])) ** 2)
+    loss.backward()
+    rng = np.random.default_rng(19)
+    dH = rng.standard_normal(Hn.shape) + 1j * rng.standard_normal(Hn.shape)
+    dy = rng.standard_normal(yn.shape) + 1j * rng.standard_normal(yn.shape)
+    dnu = rng.standard_normal(nun.shape)
+    dn = 1e-2 * b.n0
+    h = 1e-6
+
+    def L(Hx, yx, nx, nux):
+        zz, _ = oracle.eq_fd(Hx, yx, nx, b.cluster_off, nu=nux)
+        return float(np.mean(np.abs(zz - sn) ** 2))
+
+    H64, y64, nu64 = Hn.astype(np.complex128), yn.astype(np.complex128), nun.astype(np.float64)
+    num = (L(H64 + h * dH, y64 + h * dy, b.n0 + h * dn, nu64 + h * dnu)
+           - L(H64 - h * dH, y64 - h * dy, b.n0 - h * dn, nu64 - h * dnu)) / (2 * h)
+    ana = (np.sum(np.real(np.conj(host(H.grad)) * dH)) + np.sum(np.real(np.conj(host(y.grad)) * dy))
+           + float(n0.grad) * dn + float(np.sum(host(nu.grad) * dnu)))
+    nu_part = float(np.sum(host(nu.grad) * dnu))
+    print(f"directional (user nu): fd64 {num:.6e} gpu {ana:.6e} (nu part {nu_part:.3e})", flush=True)
+    assert abs(nu_part) > 0.05 * abs(ana)  # the nu direction carries weight in the check
+    assert abs(num - ana) <= TOL * abs(num)
