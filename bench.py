@@ -184,7 +184,10 @@ def compact_record(out, full_path=None):
 
 
 VARIANTS = [("pd", "fp32"), ("pd", "bf16x3"), ("pd", "bf16_refine"), ("pd", "bf16x3_refine"),
-            ("fd", "fp32"), ("fd", "bf16x3"), ("fd", "bf16_refine"), ("fd", "bf16x3_refine")]
+            ("fd", "fp32"), ("fd", "bf16x3"), ("fd", "bf16x3_refine")]
+# FD with the single-BF16 Gram is refused by the library (EQ_ENOTSUP): its
+# fusion weights come from diag(A_c^-1) of the rounded Gram and miss the
+# 2e-4 gate after refinement.
 
 
 def _per_call(fn, steps):
@@ -354,6 +357,8 @@ def extra_measurements(Hn, yn, n0, off, H, y, steps):
     for mode in ("pd", "fd"):
         fn = api.eq_pd if mode == "pd" else api.eq_fd
         for prec in ("fp32", "bf16x3", "bf16_refine", "bf16x3_refine"):
+            if mode == "fd" and prec == "bf16_refine":
+                continue
             t = _timed(lambda: fn(H3, y3, n03, off3, precision=prec), steps, 3)
             z, s2, info = fn(H3, y3, n03, off3, precision=prec, return_info=True)
             routed = ((info & (1 << 30)) != 0)
