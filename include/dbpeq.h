@@ -32,8 +32,9 @@
  *                  condition number above EQ_COND_LIMIT or a failed FP32/BF16
  *                  pivot, and its subcarrier was re-solved in FP64 on the GPU
  *                  (informational, not an error).
- * No exceptions and no global mutable state cross the ABI; concurrent calls on
- * different streams are safe when they use different workspaces.
+ * No exceptions and no global mutable state cross the ABI (except the plans,
+ * their tuning cache and the device array of eq_pd_noalloc); concurrent calls
+ * on different streams are safe when they use different workspaces.
  */
 #ifndef DBPEQ_H
 #define DBPEQ_H
@@ -155,6 +156,24 @@ eq_status eq_pd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
 eq_status eq_fd(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
                 const float *nu, eq_c32 *z, float *sigma2, int32_t *info,
                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* eq_pd without a caller workspace, for callers that cannot allocate device
+   memory: code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc.  Arguments, results and error behaviour are those of
+   eq_pd without the workspace.  The FP64 re-solve queue lives instead in a
+   library-owned device array of EQ_NOALLOC_SCRATCH_BYTES bytes on each GPU
+   the call runs on, held until the process ends; W above EQ_NOALLOC_MAX_W
+   returns EQ_ENOTSUP before any HIP call.  The call allocates nothing: it
+   clears the queue's counters with a fill kernel on `stream`, then launches
+   eq_pd's kernels.  All calls on one GPU share that GPU's array, so calls
+   that overlap on one GPU (other streams, other host threads) race: the
+   caller orders them.  The first call on a device looks up the array's
+   device address (hipGetSymbolAddress) with that device current, so make
+   it outside graph capture; `stream` must belong to the current device. */
+#define EQ_NOALLOC_MAX_W 262144
+#define EQ_NOALLOC_SCRATCH_BYTES (256 + 4 * EQ_NOALLOC_MAX_W)
+eq_status eq_pd_noalloc(const eq_problem *p, const eq_c32 *H, const eq_c32 *y,
+                        eq_c32 *z, float *sigma2, int32_t *info, void *stream);
 
 /* Several receive vectors per channel matrix (Section VI-B): the OFDM
    symbols of one coherence interval share H, so the Gram matrices, their

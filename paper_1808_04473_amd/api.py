@@ -55,6 +55,8 @@ SIGNATURES = [
                         c_void_p, c_size_t, c_void_p]),
     ("eq_fd", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                         c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("eq_pd_noalloc", c_int32, [POINTER(EqProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p]),
     ("eq_pd_sym", c_int32, [POINTER(EqProblem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_size_t, c_void_p]),
     ("eq_fd_sym", c_int32, [POINTER(EqProblem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -229,6 +231,24 @@ def eq_pd(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, ou
     st = lib.eq_pd(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info),
                    _ptr(ws), ws.numel(), _stream())
     _check("eq_pd", st)
+    return (z, s2, info) if return_info else (z, s2)
+
+
+NOALLOC_MAX_W = 262144  # EQ_NOALLOC_MAX_W
+
+
+def eq_pd_noalloc(H, y, n0, cluster_off, precision="fp32", es=1.0, return_info=False, out=None,
+                  equalizer="lmmse"):
+    """eq_pd with the library's own device array as its workspace (W at most
+    NOALLOC_MAX_W).  The C call allocates nothing; pass `out` = (z, sigma2,
+    info) to keep this wrapper from allocating the outputs."""
+    lib = load_library()
+    H, y = _check_inputs(H, y)
+    W, B, U = H.shape
+    prob, _off = make_problem(W, B, U, cluster_off, n0, es, precision, equalizer)
+    z, s2, info = _outputs(out, (W, U), (W, U), (W,), H.device)
+    st = lib.eq_pd_noalloc(ctypes.byref(prob), _ptr(H), _ptr(y), _ptr(z), _ptr(s2), _ptr(info), _stream())
+    _check("eq_pd_noalloc", st)
     return (z, s2, info) if return_info else (z, s2)
 
 

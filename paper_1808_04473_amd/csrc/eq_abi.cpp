@@ -63,8 +63,12 @@ void fill_fwd(FwdArgs &a, const eq_problem *p) {
   a.zsw = p->U;
 }
 
-eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
-                  eq_c32 *z, float *s2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+}  // namespace
+
+namespace dbpeq {
+
+eq_status forward_validate(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                           const eq_c32 *z, const float *s2, const int32_t *info) {
   eq_status st = check_problem(p);
   if (st != EQ_OK) return st;
   // FD fuses with weights from diag(A_c^{-1}) of the local Grams; a refinement
@@ -75,7 +79,16 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   if (!H || !y || !z) return EQ_EINVAL;
   if (!aligned(H, 8) || !aligned(y, 8) || !aligned(z, 8)) return EQ_EINVAL;
   if ((s2 && !aligned(s2, 4)) || (info && !aligned(info, 4)) || (nu && !aligned(nu, 4))) return EQ_EINVAL;
-  if (!ws || ws_bytes < ws_bytes_for(p) || !aligned(ws, 4)) return EQ_EWORKSPACE;
+  return EQ_OK;
+}
+
+size_t forward_ws_bytes(const eq_problem *p) { return ws_bytes_for(p); }
+
+// Launches of a validated forward call with a workspace of at least
+// forward_ws_bytes(p) bytes whose first kWsHeader bytes are zero.
+eq_status forward_launch(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                         eq_c32 *z, float *s2, int32_t *info, void *ws, hipStream_t s) {
+  if (p->W == 0) return EQ_OK;
   FwdArgs a;
   fill_fwd(a, p);
   a.H = reinterpret_cast<const float2 *>(H);
@@ -84,11 +97,9 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   a.z = reinterpret_cast<float2 *>(z);
   a.s2 = s2;
   a.info = info;
-  // the workspace starts zero-filled and the re-solve kernel leaves it so
   a.fb_count = reinterpret_cast<int32_t *>(ws);
   a.fb_done = a.fb_count + 1;
   a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (p->equalizer == EQ_MRC) {
     const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
     return launch_mrc(a, fd, prec, s) == hipSuccess ? EQ_OK : EQ_EHIP;
@@ -96,6 +107,19 @@ eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y
   if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
   if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
   return EQ_OK;
+}
+
+}  // namespace dbpeq
+
+namespace {
+
+eq_status forward(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                  eq_c32 *z, float *s2, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  eq_status st = forward_validate(p, fd, H, y, nu, z, s2, info);
+  if (st != EQ_OK || p->W == 0) return st;
+  if (!ws || ws_bytes < ws_bytes_for(p) || !aligned(ws, 4)) return EQ_EWORKSPACE;
+  // the workspace starts zero-filled and the re-solve kernel leaves it so
+  return forward_launch(p, fd, H, y, nu, z, s2, info, ws, reinterpret_cast<hipStream_t>(stream));
 }
 
 // Several receive vectors per channel matrix: Y [W][nsym][B], Z [W][nsym][U].

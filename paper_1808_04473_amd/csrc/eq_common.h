@@ -79,6 +79,15 @@ hipError_t launch_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 hipError_t launch_symbols_lama(const FwdArgs &a, bool fd, int prec, hipStream_t s);
 
 hipError_t launch_backward(const BwdArgs &a, bool fd, int ntasks, hipStream_t s);
+
+// Forward calls (eq_abi.cpp), split for the entry point with a library-owned
+// workspace: argument checks (no HIP call), workspace bytes, and the launches
+// (the workspace's first 256 bytes must be zero).
+eq_status forward_validate(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                           const eq_c32 *z, const float *s2, const int32_t *info);
+size_t forward_ws_bytes(const eq_problem *p);
+eq_status forward_launch(const eq_problem *p, bool fd, const eq_c32 *H, const eq_c32 *y, const float *nu,
+                         eq_c32 *z, float *s2, int32_t *info, void *ws, hipStream_t s);
 int backward_tasks(int W, int U, int C, bool fd, int *spw);
 
 inline int ut_for(int U) { return U <= 16 ? 16 : 32; }

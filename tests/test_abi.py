@@ -328,3 +328,17 @@ def test_binding_checks_caller_outputs():
     assert api._check_nu(None, W, C, U, cpu) is None
     with pytest.raises(ValueError):
         api._check_ws(torch.empty(64, dtype=torch.float32), cpu)
+
+
+def test_noalloc_validates_before_any_hip_call(lib):
+    """eq_pd_noalloc checks its arguments like eq_pd, and refuses W above the
+    capacity of its device array (EQ_ENOTSUP), before any HIP call."""
+    import ctypes as ct
+    bad, _k1 = _prob(n0=0.0)
+    assert lib.eq_pd_noalloc(ct.byref(bad), A, A, A, A, A, None) == EINVAL
+    ok, _k2 = _prob()
+    assert lib.eq_pd_noalloc(ct.byref(ok), None, A, A, A, A, None) == EINVAL
+    big, _k3 = _prob(W=api.NOALLOC_MAX_W + 1)
+    assert lib.eq_pd_noalloc(ct.byref(big), A, A, A, A, A, None) == ENOTSUP
+    txt = open(HEADER).read()
+    assert f"#define EQ_NOALLOC_MAX_W {api.NOALLOC_MAX_W}" in txt
