@@ -491,6 +491,74 @@ def symbols_main(args, dev):
     return 0
 
 
+def focused_main(args, dev):
+    """--workload b1024 | ragged | adjoint: one workload timed alone, for
+    focused rocprofv3 runs (one JSON line; not the headline metric).
+
+    b1024:   B = 1024 antennas in 16 clusters of 64, U = 32, 4 frames x 1200
+             subcarriers (1.3 GB of H), every form in --variants;
+    ragged:  4 independent batches of 4096 ragged systems (--variants modes);
+    adjoint: FD forward and adjoint (grad H, y, N0) on the headline systems."""
+    import torch
+    from paper_1808_04473_amd import api, synth
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib, dev)
+    res = {}
+    if args.workload == "b1024":
+        c3 = [synth.config_batch(3, 10.0, frame=f) for f in range(4)]
+        H = torch.from_numpy(np.concatenate([b.H for b in c3])).to(dev)
+        y = torch.from_numpy(np.concatenate([b.y for b in c3])).to(dev)
+        n0, off = c3[0].n0, c3[0].cluster_off
+        W, Bb, Ub = H.shape
+        variants = [v for v in VARIANTS] if args.variants == "all" else \
+            [tuple(v.split(":")) for v in args.variants.split(",")]
+        for mode, prec in variants:
+            fn = api.eq_pd if mode == "pd" else api.eq_fd
+            t = _timed(lambda: fn(H, y, n0, off, precision=prec), args.steps, args.warmup)
+            t["systems_per_s"] = W / (t["call_ms_mean"] * 1e-3)
+            t["alg_GBps"] = W * bytes_per_system(Bb, Ub) / (t["call_ms_mean"] * 1e-3) / 1e9
+            t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+            res[f"{mode}_{prec}"] = t
+        workload = f"B={Bb}, C=16, U={Ub}, {W} systems per call"
+    elif args.workload == "ragged":
+        rbs = [synth.make_ragged(4096, seed=synth.BASE_SEED + 4 + 17 * k) for k in range(4)]
+        pools = [(torch.from_numpy(rb.H_pool).to(dev), torch.from_numpy(rb.y_pool).to(dev)) for rb in rbs]
+        nbytes = sum(int(np.sum(rb.B.astype(np.int64) * rb.U * 8 + rb.B * 8 + rb.U * 12)) for rb in rbs)
+        modes = ["pd", "fd"] if args.variants == "all" else [v.split(":")[0] for v in args.variants.split(",")]
+        for mode in modes:
+            plans = [api.Plan.from_ragged(rb, fd=mode == "fd") for rb in rbs]
+
+            def run_all():
+                for pl, (hp, yp) in zip(plans, pools):
+                    pl.execute(hp, yp)
+            t = _timed(run_all, args.steps, args.warmup)
+            t["systems_per_s"] = 4 * 4096 / (t["call_ms_mean"] * 1e-3)
+            t["alg_GBps"] = nbytes / (t["call_ms_mean"] * 1e-3) / 1e9
+            t["hbm_frac"] = t["alg_GBps"] / HBM_PEAK_GBS
+            t["alg_bytes_per_call"] = nbytes
+            res[f"{mode}_fp32"] = t
+            for pl in plans:
+                pl.close()
+        workload = "4 batches x 4096 ragged systems (B_c in {16,24,32,48,64}, C in 2..16, U in {8,16,24,32})"
+    else:  # adjoint
+        Hn, yn, n0, off = make_inputs(args.frames)
+        H, y = torch.from_numpy(Hn).to(dev), torch.from_numpy(yn).to(dev)
+        W = H.shape[0]
+        gz = torch.randn(W, U, dtype=torch.complex64, device=dev)
+        tf = _timed(lambda: api.eq_fd(H, y, n0, off), args.steps, args.warmup)
+        tb = _timed(lambda: api.eq_fd_backward(H, y, n0, off, gz=gz), args.steps, args.warmup)
+        # the adjoint reads H, y and grad_z and writes grad_H and grad_y
+        bb = W * (2 * B * U * 8 + 2 * B * 8 + U * 8)
+        tb.update({"systems_per_s": W / (tb["call_ms_mean"] * 1e-3),
+                   "alg_GBps": bb / (tb["call_ms_mean"] * 1e-3) / 1e9, "alg_bytes_per_call": bb})
+        tb["hbm_frac"] = tb["alg_GBps"] / HBM_PEAK_GBS
+        res = {"fd_forward_fp32": tf, "fd_backward_fp32": tb}
+        workload = f"FD B={B}, C={C}, U={U}, {W} systems per call"
+    print(json.dumps({"workload": args.workload, "config": {"workload": workload}, "steps": args.steps,
+                      "results": res}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -512,6 +580,8 @@ def main(argv=None):
     ap.add_argument("--nsym", type=int, default=1,
                     help="time eq_pd_sym / eq_fd_sym with this many receive vectors per channel "
                          "matrix instead of the headline workload (for focused profiles)")
+    ap.add_argument("--workload", choices=["headline", "b1024", "ragged", "adjoint"], default="headline",
+                    help="time one other workload alone (focused profiles; not the headline metric)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (PMC scale reference)")
     args = ap.parse_args(argv)
@@ -523,7 +593,7 @@ def main(argv=None):
 
     # the oracle's worker processes are forked before anything touches the GPU
     cpu = None
-    if not args.no_cpu_baseline and args.nsym == 1:
+    if not args.no_cpu_baseline and args.nsym == 1 and args.workload == "headline":
         cpu = CpuBaseline(args.frames, args.cpu_seconds, args.cpu_cores or None)
     try:
         return _gpu_main(args, cpu)
@@ -541,6 +611,8 @@ def _gpu_main(args, cpu):
 
     if args.nsym > 1:
         return symbols_main(args, dev)
+    if args.workload != "headline":
+        return focused_main(args, dev)
 
     t_gen = time.perf_counter()
     Hn, yn, n0, off = make_inputs(args.frames)
