@@ -36,18 +36,21 @@ def bytes_per_system(B=B, U=U):
     return B * U * 8 + B * 8 + U * 8 + U * 4
 
 
-def kernel_source_sha():
+def kernel_source_sha(files=None):
+    """sha256[:16] over the kernel sources `files` (names under csrc/; all of
+    them when None)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1808_04473_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    names = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp"))) if files is None \
+        else list(files)
+    for f in names:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(variant):
     """HBM traffic per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current sources of that kernel (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -56,7 +59,7 @@ def load_traffic(variant):
     except (OSError, ValueError):
         return None
     e = t.get(variant)
-    if not e or e.get("source_sha") != kernel_source_sha():
+    if not e or e.get("source_sha") != kernel_source_sha(e.get("sources")):
         return None
     return e.get("bytes_per_launch")
 
