@@ -305,9 +305,10 @@ const char *eq_status_string(eq_status s);
 int32_t eq_abi_version(void);
 
 /* Measurement aid, not part of the equaliser: reads the `bytes` bytes (a
-   multiple of 16; device pointer aligned to 16) at `buf` once, with 16-byte
-   nontemporal loads spread over the whole device, and may write one float to
-   the device pointer `sink`.  bytes / (time of the call on `stream`) is the
+   multiple of 16; device pointer aligned to 16) at `buf` once, one wave per
+   64 KiB of consecutive bytes with 8-byte nontemporal loads (the access
+   pattern of the equaliser's streams), and may write one float to the
+   device pointer `sink`.  bytes / (time of the call on `stream`) is the
    practical HBM read ceiling against which the equaliser's streams are
    compared.  bytes == 0 is a no-op; bad arguments give EQ_EINVAL. */
 eq_status eq_probe_read(const void *buf, size_t bytes, float *sink, void *stream);

@@ -100,6 +100,8 @@ SHAPES = [
     (3, 12, 4, list(range(13))),           # one antenna per cluster (B_c = 1 < U)
     (4, 40, 24, [0, 8, 40]),               # B_c = 8 < U = 24 in FD
     (2, 300, 8, [0, 100, 300]),
+    (5, 40, 6, list(range(0, 41, 2))),      # C = 20 > 16: FD rounds span subcarriers
+    (3, 68, 16, list(range(0, 69, 4))),     # C = 17, B_c = 4 < U = 16
 ]
 
 
