@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define EQ_ABI_VERSION 2
+#define EQ_ABI_VERSION 3
 #define EQ_MAX_U 32          /* users per system */
 #define EQ_MAX_B 65535       /* antennas per system */
 #define EQ_MAX_C 1024        /* clusters per system */
@@ -274,30 +274,47 @@ typedef struct {
 
 typedef struct eq_plan eq_plan;
 
-/* Validates the descriptors, sorts the systems into cost-ordered work items,
-   uploads the descriptor table (the plan owns this device memory) and loads
-   the tile choice from the autotune cache (`tune_cache_path`, NULL = the
-   DBPEQ_TUNE_CACHE environment variable, else no cache).  fd selects FD
-   (1) or PD (0).  Returns EQ_ENOMEM if the table cannot be allocated. */
+/* Validates the descriptors and builds the plan's work items, all run by
+   one persistent launch: PD rounds of up to 64/UT whole systems of equal U
+   (UT = 16 or 32, the tile class), PD row pieces of the systems longer than
+   the class's piece rows (each piece's partial Gram goes to a plan-owned
+   slot; the last piece of a system sums them in piece order and solves), FD
+   rounds of up to 64/UT clusters of equal U (each cluster's fusion terms go
+   to a slot; the last cluster of a system fuses them in cluster order).
+   Results do not depend on the launch shape beyond the rounding of those
+   sums.  The launch shape (waves per CU; piece rows per class) comes from
+   the autotune cache (`tune_cache_path`, NULL = the DBPEQ_TUNE_CACHE
+   environment variable, else no cache), whose entries are keyed by device,
+   mode, precision and, for the piece rows, tile class, so that any batch of
+   the same classes reuses them.  fd selects FD (1) or PD (0).  The plan owns
+   its device memory (descriptor table, items, slots); EQ_ENOMEM if it cannot
+   be allocated. */
 eq_status eq_plan_create(eq_plan **out, const eq_sys *host_desc, int32_t nsys,
                          const int32_t *host_cluster_sizes, int32_t n_cluster_sizes,
                          int32_t fd, int32_t precision, float es,
                          const char *tune_cache_path);
 
 /* Equalises every system of the plan: z, sigma2 (may be NULL) and info
-   ([nsys], may be NULL).  The first call on a plan autotunes (when the cache
-   has no entry) and captures one persistent launch into a hipGraph; later
-   calls with the same pools and stream replay the graph.  Stream-ordered. */
+   ([nsys], may be NULL).  The first call on a plan autotunes what the cache
+   has no entry for (timing the launch on these pools, which it overwrites
+   as a normal call would) and captures the launch into a hipGraph; later
+   calls with the same pools replay the graph.  Stream-ordered, except that a call
+   with other pools first waits for the plan's previous launch to finish (on
+   the host) before it replaces the graph. */
 eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypool,
                           eq_c32 *zpool, float *s2pool, int32_t *info, void *stream);
 
-/* Launch shape of the plan: out_shape[0] = persistent workgroups (one
-   wave each), out_shape[1] = 1 if PD work items hold half a round of systems
-   (else a full round of 64/UT systems of equal U); *out_tasks = work items. */
+/* Launch shape of the plan, per tile class k (EQ_PLAN_CLASSES of them: the
+   padded user count 16, 32), in out_shape[5k .. 5k+4] (out_shape holds
+   5 * EQ_PLAN_CLASSES entries, may be NULL): systems of the class, work
+   items, PD row pieces (FD: clusters), PD piece rows (0 = systems are not
+   cut; always 0 for FD and the refining forms), persistent waves of the
+   launch.  *out_tasks (may be NULL) = work items of all classes. */
+#define EQ_PLAN_CLASSES 2
 eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_shape, int32_t *out_tasks);
 
-/* Frees the plan and every device buffer and graph it holds (a null plan
-   is a no-op).  The plan is gone on return either way; EQ_EHIP reports that
+/* Waits on the host for the plan's last launch, then frees the plan and
+   every device buffer, stream and graph it holds (a null plan is a no-op).  The plan is gone on return either way; EQ_EHIP reports that
    one of the releases failed. */
 eq_status eq_plan_destroy(eq_plan *plan);
 

@@ -441,6 +441,10 @@ def eq_fd_backward(H, y, n0, cluster_off, gz=None, gs=None, nu=None, es=1.0):
     return gH, gy, gn0, gnu
 
 
+PLAN_CLASSES = 2        # EQ_PLAN_CLASSES
+PLAN_CLASS_NAMES = ("ut16", "ut32")
+
+
 class Plan:
     """A ragged batch of independent systems (eq_plan_* of the C ABI).
 
@@ -512,10 +516,20 @@ class Plan:
         return z, s2, info
 
     def describe(self):
-        shape = (c_int32 * 2)()
+        """Launch shape per tile class (padded users 16 / 32): systems, work
+        items, PD row pieces (FD: clusters) and PD piece rows (0 = systems
+        are not cut); the persistent waves of the launch and the total number
+        of work items."""
+        shape = (c_int32 * (5 * PLAN_CLASSES))()
         nt = c_int32()
         _check("eq_plan_describe", self._lib.eq_plan_describe(self._h, shape, ctypes.byref(nt)))
-        return {"grid": shape[0], "half_items": shape[1], "tasks": nt.value}
+        classes = {}
+        for k, name in enumerate(PLAN_CLASS_NAMES):
+            v = shape[5 * k:5 * k + 5]
+            if v[0]:
+                key = "clusters" if self.fd else "pieces"
+                classes[name] = {"systems": v[0], "items": v[1], key: v[2], "piece_rows": v[3]}
+        return {"classes": classes, "grid": shape[4], "tasks": nt.value}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,6 +1,7 @@
-// Ragged-batch plans: host-side descriptor table, cost-sorted work items, the
-// launch-shape autotuner (with a JSON cache) and hipGraph capture of the
-// persistent launch.
+// Ragged-batch plans: host-side descriptor table, cost-ordered work items
+// (rounds of whole systems, row pieces of large systems, rounds of clusters),
+// the autotuner (with a JSON cache keyed by device, mode, precision and tile
+// class) and hipGraph capture of the launch.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -15,135 +16,234 @@
 
 using namespace dbpeq;
 
+namespace {
+constexpr int kClasses = EQ_PLAN_CLASSES;  // tile classes: padded users 16, 32
+constexpr int kDefaultRows = 256;
+constexpr int kDefaultWpc = 8;
+inline int cls_of(int ut) { return ut == 16 ? 0 : 1; }
+constexpr int kHeads = kQueues * kQueueStride;  // scratch words of the queue heads
+constexpr int kList = kHeads + 64;              // first word of the FP64 list
+}  // namespace
+
 struct eq_plan {
   int fd = 0, prec = 0;
   float es = 1.f;
-  int nsys = 0;
+  int nsys = 0, ncl = 0;
   std::vector<RSys> sys;
   std::vector<int32_t> offs;
-  // tuned launch shape
-  int grid = 0;       // persistent workgroups (one wave each)
-  int half = 0;       // PD: 1 = work items of half a round of systems
-  bool tuned = false;
-  std::string cache_path, key;
+  std::vector<int32_t> cl_sys;  // system of each global cluster
+  // launch shape: waves per CU of the persistent grid, and per tile class
+  // the row count above which a PD system is cut into pieces (0 = never)
+  int wpc = kDefaultWpc;
+  int piece_rows[kClasses] = {kDefaultRows, kDefaultRows};
+  bool tuned_launch = false;
+  bool tuned_rows[kClasses] = {false, false};
+  int built_rows[kClasses] = {-1, -1};  // piece_rows the device tables were built for
+  std::string cache_path;
+  int cus = 0;
+  // per class: systems, items, pieces (PD) or clusters (FD)
+  int n_sys[kClasses] = {0, 0}, n_items[kClasses] = {0, 0}, n_pieces[kClasses] = {0, 0};
+  int ntasks = 0;
+  size_t cap_slots = 0;
   // device memory owned by the plan
   RSys *d_sys = nullptr;
   int32_t *d_offs = nullptr;
+  int32_t *d_clsys = nullptr;
   RTask *d_tasks = nullptr;
   int32_t *d_order = nullptr;
-  int32_t *d_scratch = nullptr;  // [0] queue head, [1] FP64 count, [64..] FP64 list
-  int ntasks = 0;
-  int tasks_half = -1;            // `half` the device task table was built for
+  int32_t *d_scratch = nullptr;  // [0, kHeads) queue heads, [kHeads] FP64 count,
+                                 // [kList, kList + nsys) FP64 list, [kList + nsys, kList + 2 nsys) arrivals
+  float *d_part = nullptr;       // PD partial slots
+  float *d_fpart = nullptr;      // FD fusion terms
+  int32_t *d_fcode = nullptr;    // FD failure codes
   // captured graph and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void *gargs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t cap = nullptr;
+  // recorded after every graph launch: the executable graph is destroyed
+  // (re-capture, plan destruction) only once its last launch has finished
+  hipEvent_t done = nullptr;
 };
 
 namespace {
 
-double sys_cost(const RSys &d, bool fd) {
-  const double ut = d.ut;
-  // Gram work (B * UT^2) plus the small solves (UT^3 per system or cluster)
-  return (double)d.B * ut * ut + (fd ? d.C : 1) * ut * ut * ut * 4.0;
-}
+bool refining(const eq_plan &p) { return p.prec == EQ_BF16_REFINE || p.prec == EQ_BF16X3_REFINE; }
 
-// Work items: FD = one system each; PD = up to `per` systems of equal U.
-void build_tasks(const eq_plan &p, int half, std::vector<RTask> &tasks, std::vector<int32_t> &order) {
-  std::vector<int32_t> idx(p.nsys);
-  for (int k = 0; k < p.nsys; ++k) idx[k] = k;
-  const bool fd = p.fd != 0;
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-    if (!fd && p.sys[a].U != p.sys[b].U) return p.sys[a].U < p.sys[b].U;
-    return sys_cost(p.sys[a], fd) > sys_cost(p.sys[b], fd);
-  });
-  order = idx;
-  tasks.clear();
+// Rows per row block of the streaming layout (the unit of a piece).
+int rows_per_block(int ut) { return 8 * (64 / ut); }
+
+double gram_cost(int rows, int ut) { return (double)rows * ut * ut; }
+double solve_cost(int ut) { return 4.0 * ut * ut * ut; }
+
+// Builds the work items for the given piece rows (PD) and uploads them with
+// the updated descriptor table; the items are sorted by cost, largest first.
+eq_status build_items(eq_plan *p, const int (&rows)[kClasses]) {
+  bool same = p->d_tasks != nullptr;
+  for (int c = 0; c < kClasses; ++c) same = same && p->built_rows[c] == rows[c];
+  if (same) return EQ_OK;
+  std::vector<RTask> tasks;
   std::vector<double> cost;
-  int k = 0;
-  while (k < p.nsys) {
-    const RSys &d = p.sys[idx[k]];
-    int per = fd ? 1 : 64 / d.ut;
-    if (!fd && half) per = per > 1 ? per / 2 : 1;
-    int n = 0;
-    double c = 0.0;
-    while (n < per && k + n < p.nsys && p.sys[idx[k + n]].U == d.U) {
-      c += sys_cost(p.sys[idx[k + n]], fd);
-      ++n;
+  std::vector<int32_t> order;
+  for (int c = 0; c < kClasses; ++c) p->n_sys[c] = p->n_items[c] = p->n_pieces[c] = 0;
+  for (const RSys &d : p->sys) ++p->n_sys[cls_of(d.ut)];
+  size_t nslots = 0;
+  if (!p->fd) {
+    std::vector<int32_t> whole;
+    for (int k = 0; k < p->nsys; ++k) {
+      RSys &d = p->sys[k];
+      const int cl = cls_of(d.ut);
+      const int R = refining(*p) ? 0 : rows[cl];
+      const int rpb = rows_per_block(d.ut);
+      d.npieces = 1;
+      d.slot0 = 0;
+      if (R > 0 && d.B > R) {
+        const int nb = (d.B + rpb - 1) / rpb;
+        const int per = std::max(1, R / rpb);
+        const int np = (nb + per - 1) / per;
+        d.npieces = np;
+        d.slot0 = (int32_t)nslots;
+        nslots += np;
+        for (int q = 0; q < np; ++q) {
+          const int r0 = std::min(d.B, (int)((long long)nb * q / np) * rpb);
+          const int r1 = std::min(d.B, (int)((long long)nb * (q + 1) / np) * rpb);
+          tasks.push_back(RTask{kItemPiece, d.ut, d.U, k, 0, r0, r1, q});
+          cost.push_back(gram_cost(r1 - r0, d.ut) + (q == np - 1 ? solve_cost(d.ut) : 0.0));
+          ++p->n_items[cl];
+          ++p->n_pieces[cl];
+        }
+      } else {
+        whole.push_back(k);
+      }
     }
-    tasks.push_back(RTask{k, n, d.ut, d.U});
-    cost.push_back(c);
-    k += n;
+    // rounds of up to 64/UT whole systems of equal U, largest first within a U
+    std::stable_sort(whole.begin(), whole.end(), [&](int a, int b) {
+      if (p->sys[a].U != p->sys[b].U) return p->sys[a].U < p->sys[b].U;
+      return p->sys[a].B > p->sys[b].B;
+    });
+    size_t k = 0;
+    while (k < whole.size()) {
+      const RSys &d = p->sys[whole[k]];
+      const int per = 64 / d.ut;
+      int m = 0;
+      double cst = solve_cost(d.ut);
+      while (m < per && k + m < whole.size() && p->sys[whole[k + m]].U == d.U) {
+        cst += gram_cost(p->sys[whole[k + m]].B, d.ut);
+        ++m;
+      }
+      tasks.push_back(RTask{kItemGroup, d.ut, d.U, (int32_t)order.size(), m, 0, 0, 0});
+      cost.push_back(cst);
+      ++p->n_items[cls_of(d.ut)];
+      for (int j = 0; j < m; ++j) order.push_back(whole[k + j]);
+      k += m;
+    }
+  } else {
+    // rounds of up to 64/UT clusters of equal U: the clusters of each U in
+    // system order (largest systems first), so that a system's clusters share
+    // few rounds
+    std::vector<int32_t> ks(p->nsys);
+    for (int k = 0; k < p->nsys; ++k) ks[k] = k;
+    std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) {
+      if (p->sys[a].U != p->sys[b].U) return p->sys[a].U < p->sys[b].U;
+      return p->sys[a].B > p->sys[b].B;
+    });
+    size_t k = 0;
+    while (k < ks.size()) {
+      const int U = p->sys[ks[k]].U, ut = p->sys[ks[k]].ut;
+      std::vector<int32_t> cls;
+      for (; k < ks.size() && p->sys[ks[k]].U == U; ++k) {
+        const RSys &d = p->sys[ks[k]];
+        for (int c = 0; c < d.C; ++c) cls.push_back(d.cl0 + c);
+      }
+      p->n_pieces[cls_of(ut)] += (int)cls.size();
+      const int per = 64 / ut;
+      for (size_t j = 0; j < cls.size(); j += per) {
+        const int m = (int)std::min<size_t>(per, cls.size() - j);
+        double cst = solve_cost(ut);
+        for (int q = 0; q < m; ++q) {
+          const int gc = cls[j + q];
+          const RSys &d = p->sys[p->cl_sys[gc]];
+          const int c = gc - d.cl0;
+          cst += gram_cost(p->offs[d.off_first + c + 1] - p->offs[d.off_first + c], ut);
+        }
+        tasks.push_back(RTask{kItemRound, ut, U, (int32_t)(order.size() + j), m, 0, 0, 0});
+        cost.push_back(cst);
+        ++p->n_items[cls_of(ut)];
+      }
+      order.insert(order.end(), cls.begin(), cls.end());
+    }
   }
-  // largest items first
   std::vector<int> ti(tasks.size());
   for (size_t t = 0; t < ti.size(); ++t) ti[t] = (int)t;
   std::stable_sort(ti.begin(), ti.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   std::vector<RTask> sorted;
+  sorted.reserve(tasks.size());
   for (int t : ti) sorted.push_back(tasks[t]);
-  tasks.swap(sorted);
-}
-
-eq_status upload_tasks(eq_plan *p, int half) {
-  if (p->tasks_half == half) return EQ_OK;
-  std::vector<RTask> tasks;
-  std::vector<int32_t> order;
-  build_tasks(*p, half, tasks, order);
-  // the previous table: a failed free leaves nothing this call could repair
+  p->ntasks = (int)sorted.size();
+  // the previous tables: a failed free leaves nothing this call could repair
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   p->d_tasks = nullptr;
-  if (hipMalloc(&p->d_tasks, sizeof(RTask) * tasks.size()) != hipSuccess) return EQ_ENOMEM;
-  if (hipMemcpy(p->d_tasks, tasks.data(), sizeof(RTask) * tasks.size(), hipMemcpyHostToDevice) != hipSuccess)
+  if (p->d_order) (void)hipFree(p->d_order);
+  p->d_order = nullptr;
+  if (hipMalloc(&p->d_tasks, sizeof(RTask) * std::max<size_t>(1, sorted.size())) != hipSuccess ||
+      hipMalloc(&p->d_order, sizeof(int32_t) * std::max<size_t>(1, order.size())) != hipSuccess)
+    return EQ_ENOMEM;
+  if (nslots > p->cap_slots) {
+    if (p->d_part) (void)hipFree(p->d_part);
+    p->d_part = nullptr;
+    p->cap_slots = 0;
+    if (hipMalloc(&p->d_part, sizeof(float) * kPartStride * nslots) != hipSuccess) return EQ_ENOMEM;
+    p->cap_slots = nslots;
+  }
+  if ((!sorted.empty() &&
+       hipMemcpy(p->d_tasks, sorted.data(), sizeof(RTask) * sorted.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      (!order.empty() &&
+       hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(p->d_sys, p->sys.data(), sizeof(RSys) * p->nsys, hipMemcpyHostToDevice) != hipSuccess)
     return EQ_EHIP;
-  if (hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return EQ_EHIP;
-  p->ntasks = (int)tasks.size();
-  p->tasks_half = half;
+  for (int c = 0; c < kClasses; ++c) p->built_rows[c] = rows[c];
   return EQ_OK;
 }
 
-std::string plan_key(const eq_plan &p) {
-  // shape signature: FNV-1a over every (B, U, C, cluster sizes), in order
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](uint64_t v) {
-    for (int b = 0; b < 8; ++b) {
-      h ^= (v >> (8 * b)) & 0xff;
-      h *= 1099511628211ull;
-    }
-  };
-  for (const RSys &d : p.sys) {
-    mix(d.B);
-    mix(d.U);
-    mix(d.C);
-  }
-  for (int32_t o : p.offs) mix((uint64_t)o);
-  char buf[160];
-  snprintf(buf, sizeof(buf), "gfx950/%s/p%d/n%d/%016llx", p.fd ? "fd" : "pd", p.prec, p.nsys,
-           (unsigned long long)h);
+eq_status build_current(eq_plan *p) { return build_items(p, p->piece_rows); }
+
+// Tuning cache keys: device, mode, precision and, for the piece rows, the
+// tile class, so that any batch drawn from the same distribution finds them.
+std::string key_launch(const eq_plan &p) {
+  char buf[64];
+  snprintf(buf, sizeof(buf), "gfx950/%s/p%d/launch", p.fd ? "fd" : "pd", p.prec);
+  return buf;
+}
+std::string key_rows(const eq_plan &p, int cls) {
+  char buf[64];
+  snprintf(buf, sizeof(buf), "gfx950/%s/p%d/ut%d", p.fd ? "fd" : "pd", p.prec, cls == 0 ? 16 : 32);
   return buf;
 }
 
 // The cache is a JSON object with one entry per line:
-//   "key": {"grid": G, "half": H},
-std::map<std::string, std::pair<int, int>> read_cache(const std::string &path) {
-  std::map<std::string, std::pair<int, int>> m;
+//   "<mode key>/launch": {"wpc": W},   "<mode key>/utNN": {"piece_rows": R},
+std::map<std::string, int> read_cache(const std::string &path) {
+  std::map<std::string, int> m;
   if (path.empty()) return m;
   FILE *f = fopen(path.c_str(), "r");
   if (!f) return m;
   char line[512];
   while (fgets(line, sizeof(line), f)) {
     char key[256];
-    int g = 0, hf = 0;
-    if (sscanf(line, " \"%255[^\"]\": {\"grid\": %d, \"half\": %d}", key, &g, &hf) == 3 && g > 0 &&
-        (hf == 0 || hf == 1))
-      m[key] = {g, hf};
+    int v = 0;
+    if (sscanf(line, " \"%255[^\"]\": {\"wpc\": %d}", key, &v) == 2) {
+      if (v >= 1 && v <= 64) m[key] = v;
+    } else if (sscanf(line, " \"%255[^\"]\": {\"piece_rows\": %d}", key, &v) == 2) {
+      if (v == 0 || (v >= 16 && v <= EQ_MAX_B)) m[key] = v;
+    }
   }
   fclose(f);
   return m;
 }
 
-void write_cache(const std::string &path, const std::map<std::string, std::pair<int, int>> &m) {
+bool is_launch_key(const std::string &k) { return k.size() >= 7 && k.compare(k.size() - 7, 7, "/launch") == 0; }
+
+void write_cache(const std::string &path, const std::map<std::string, int> &m) {
   if (path.empty()) return;
   const std::string tmp = path + ".tmp";
   FILE *f = fopen(tmp.c_str(), "w");
@@ -152,8 +252,8 @@ void write_cache(const std::string &path, const std::map<std::string, std::pair<
   size_t n = 0;
   for (const auto &kv : m) {
     ++n;
-    fprintf(f, "  \"%s\": {\"grid\": %d, \"half\": %d}%s\n", kv.first.c_str(), kv.second.first,
-            kv.second.second, n < m.size() ? "," : "");
+    fprintf(f, "  \"%s\": {\"%s\": %d}%s\n", kv.first.c_str(), is_launch_key(kv.first) ? "wpc" : "piece_rows",
+            kv.second, n < m.size() ? "," : "");
   }
   fprintf(f, "}\n");
   fclose(f);
@@ -172,36 +272,52 @@ RaggedArgs make_args(const eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 
   a.offs = p->d_offs;
   a.tasks = p->d_tasks;
   a.order = p->d_order;
+  a.cl_sys = p->d_clsys;
   a.counter = p->d_scratch;
-  a.fb_count = p->d_scratch + 1;
-  a.fb_list = p->d_scratch + 64;
+  a.fb_count = p->d_scratch + kHeads;
+  a.fb_list = p->d_scratch + kList;
+  a.arrive = p->d_scratch + kList + p->nsys;
+  a.part = p->d_part;
+  a.fpart = p->d_fpart;
+  a.fcode = p->d_fcode;
   a.nsys = p->nsys;
   a.ntasks = p->ntasks;
   a.es = p->es;
   return a;
 }
 
-hipError_t enqueue(const eq_plan *p, const RaggedArgs &a, int grid, hipStream_t s) {
-  hipError_t e = launch_zero_i32(p->d_scratch, 2, s);
-  if (e != hipSuccess) return e;
-  e = launch_ragged(a, p->fd != 0, p->prec, grid, s);
-  if (e != hipSuccess) return e;
-  return launch_fp64_ragged(a, p->fd != 0, s);
+// Persistent waves: CUs x waves per CU, at most one per item, and at least one
+// per queue that holds items (queue q holds the items t with t % kQueues == q).
+int grid_of(const eq_plan *p, int wpc) {
+  const int g = std::min(p->cus * wpc, p->ntasks);
+  return std::max(1, std::max(g, std::min(kQueues, p->ntasks)));
 }
 
-// Times every launch shape on the real pools and keeps the fastest.
+// Clears the queue heads, the FP64 count and the arrival counters, runs the
+// persistent launch, then (fp64) the FP64 re-solve of the systems it queued.
+hipError_t enqueue(const eq_plan *p, int wpc, bool fp64, const eq_c32 *H, const eq_c32 *y, eq_c32 *z,
+                   float *s2, int32_t *info, hipStream_t s) {
+  hipError_t e = launch_zero_i32(p->d_scratch, kList + 2 * p->nsys, s);
+  if (e != hipSuccess) return e;
+  const RaggedArgs a = make_args(p, H, y, z, s2, info);
+  if ((e = launch_ragged(a, p->fd != 0, p->prec, grid_of(p, wpc), s)) != hipSuccess) return e;
+  return fp64 ? launch_fp64_ragged(a, p->fd != 0, s) : hipSuccess;
+}
+
+// Capture stream and launch event (created once per plan).
+hipError_t make_streams(eq_plan *p) {
+  hipError_t e = hipSuccess;
+  if (!p->cap && (e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) != hipSuccess) return e;
+  if (!p->done && (e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// Times the launch on the real pools for each candidate of whatever the
+// cache did not hold: first the waves per CU (with the current piece rows),
+// then, for PD outside the refining forms, the piece rows of each tile class
+// that has systems.  Keeps the fastest of each.
 eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, float *s2, int32_t *info,
                    hipStream_t s) {
-  int cus = 256;
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
-  const int waves[] = {1, 2, 4, 8};
-  const int nh = p->fd ? 1 : 2;
-  // destroyed on every exit, the error returns of the loop included
   struct Events {
     hipEvent_t e[2] = {nullptr, nullptr};
     ~Events() {
@@ -210,46 +326,79 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
     }
   } ev;
   if (hipEventCreate(&ev.e[0]) != hipSuccess || hipEventCreate(&ev.e[1]) != hipSuccess) return EQ_EHIP;
-  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
-  float best = 1e30f;
-  int bg = cus * 2, bh = 0;
-  for (int hf = 0; hf < nh; ++hf) {
-    eq_status st = upload_tasks(p, hf);
-    if (st != EQ_OK) return st;
-    for (int wv : waves) {
-      const int grid = cus * wv;
-      RaggedArgs a = make_args(p, H, y, z, s2, info);
-      float tmin = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
-        if (hipEventRecord(e0, s) != hipSuccess) return EQ_EHIP;
-        if (enqueue(p, a, grid, s) != hipSuccess) return EQ_EHIP;
-        if (hipEventRecord(e1, s) != hipSuccess) return EQ_EHIP;
-        if (hipEventSynchronize(e1) != hipSuccess) return EQ_EHIP;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return EQ_EHIP;
-        tmin = ms < tmin ? ms : tmin;
-      }
-      if (tmin < best) {
-        best = tmin;
-        bg = grid;
-        bh = hf;
+  eq_status st = EQ_OK;
+  auto time = [&](const int (&rows)[kClasses], int wpc, float &best) -> eq_status {
+    eq_status bst = build_items(p, rows);
+    if (bst != EQ_OK) return bst;
+    best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(ev.e[0], s) != hipSuccess || enqueue(p, wpc, false, H, y, z, s2, info, s) != hipSuccess ||
+          hipEventRecord(ev.e[1], s) != hipSuccess || hipEventSynchronize(ev.e[1]) != hipSuccess)
+        return EQ_EHIP;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev.e[0], ev.e[1]) != hipSuccess) return EQ_EHIP;
+      best = std::min(best, ms);
+    }
+    return EQ_OK;
+  };
+  auto m = read_cache(p->cache_path);
+  if (!p->tuned_launch) {
+    // the kernel's registers (2 waves per SIMD) hold 8 waves per CU, and its
+    // LDS (17.9 KB per one-wave workgroup) would not hold more than 9; larger
+    // grids only queue workgroups that find the queues empty
+    const int wpcs[] = {4, 6, 8};
+    float tbest = 1e30f;
+    for (int w : wpcs) {
+      float t = 0.f;
+      if ((st = time(p->piece_rows, w, t)) != EQ_OK) return st;
+      if (t < tbest) {
+        tbest = t;
+        p->wpc = w;
       }
     }
+    p->tuned_launch = true;
+    m[key_launch(*p)] = p->wpc;
   }
-  p->grid = bg;
-  p->half = bh;
-  p->tuned = true;
-  auto m = read_cache(p->cache_path);
-  m[p->key] = {bg, bh};
+  for (int c = 0; c < kClasses; ++c) {
+    if (p->tuned_rows[c] || p->fd || refining(*p) || p->n_sys[c] == 0) continue;
+    const int cand[] = {0, 128, 256, 384, 512};
+    float tbest = 1e30f;
+    int best = p->piece_rows[c];
+    for (int r : cand) {
+      int rows[kClasses] = {p->piece_rows[0], p->piece_rows[1]};
+      rows[c] = r;
+      float t = 0.f;
+      if ((st = time(rows, p->wpc, t)) != EQ_OK) return st;
+      if (t < tbest) {
+        tbest = t;
+        best = r;
+      }
+    }
+    p->piece_rows[c] = best;
+    p->tuned_rows[c] = true;
+    m[key_rows(*p, c)] = best;
+  }
   write_cache(p->cache_path, m);
-  return EQ_OK;
+  return build_current(p);
 }
 
 void drop_graph(eq_plan *p) {
+  // a launch still in flight uses the executable graph's kernel arguments; a
+  // failed wait leaves nothing better than destroying it
+  if (p->exec && p->done) (void)hipEventSynchronize(p->done);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
+}
+
+// Whether every tuned quantity the plan uses is known.
+bool all_tuned(const eq_plan *p) {
+  if (!p->tuned_launch) return false;
+  if (p->fd || refining(*p)) return true;
+  for (int c = 0; c < kClasses; ++c)
+    if (!p->tuned_rows[c] && p->n_sys[c] > 0) return false;
+  return true;
 }
 
 }  // namespace
@@ -298,7 +447,9 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const 
     r.n0 = d.n0;
     r.rho = d.n0 / es;
     r.ut = ut_for(d.U);
-    r.pad = 0;
+    r.npieces = 1;
+    r.slot0 = 0;
+    r.cl0 = (int32_t)p->cl_sys.size();
     r.off_first = (int32_t)p->offs.size();
     int acc = 0;
     p->offs.push_back(0);
@@ -310,35 +461,55 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const 
       }
       acc += sz;
       p->offs.push_back(acc);
+      p->cl_sys.push_back(k);
     }
     if (acc != d.B) {
       delete p;
       return EQ_EINVAL;
     }
   }
+  p->ncl = (int)p->cl_sys.size();
   p->cache_path = tune_cache_path ? tune_cache_path : (getenv("DBPEQ_TUNE_CACHE") ? getenv("DBPEQ_TUNE_CACHE") : "");
-  p->key = plan_key(*p);
-  auto m = read_cache(p->cache_path);
-  auto it = m.find(p->key);
-  if (it != m.end()) {
-    p->grid = it->second.first;
-    p->half = it->second.second;
-    p->tuned = true;
+  {
+    auto m = read_cache(p->cache_path);
+    auto it = m.find(key_launch(*p));
+    if (it != m.end()) {
+      p->wpc = it->second;
+      p->tuned_launch = true;
+    }
+    for (int c = 0; c < kClasses; ++c) {
+      auto jt = m.find(key_rows(*p, c));
+      if (jt != m.end()) {
+        p->piece_rows[c] = jt->second;
+        p->tuned_rows[c] = true;
+      }
+    }
+  }
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    p->cus = hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+                     prop.multiProcessorCount > 0
+                 ? prop.multiProcessorCount
+                 : 256;
   }
   bool ok = hipMalloc(&p->d_sys, sizeof(RSys) * nsys) == hipSuccess &&
             hipMalloc(&p->d_offs, sizeof(int32_t) * p->offs.size()) == hipSuccess &&
-            hipMalloc(&p->d_order, sizeof(int32_t) * nsys) == hipSuccess &&
-            hipMalloc(&p->d_scratch, sizeof(int32_t) * (64 + (size_t)nsys)) == hipSuccess;
+            hipMalloc(&p->d_scratch, sizeof(int32_t) * (kList + 2 * (size_t)nsys)) == hipSuccess;
+  if (ok && fd)
+    ok = hipMalloc(&p->d_clsys, sizeof(int32_t) * p->ncl) == hipSuccess &&
+         hipMalloc(&p->d_fpart, sizeof(float) * 4 * kFusionStride * (size_t)p->ncl) == hipSuccess &&
+         hipMalloc(&p->d_fcode, sizeof(int32_t) * 2 * (size_t)p->ncl) == hipSuccess;
   if (!ok) {
     eq_plan_destroy(p);
     return EQ_ENOMEM;
   }
-  if (hipMemcpy(p->d_sys, p->sys.data(), sizeof(RSys) * nsys, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_offs, p->offs.data(), sizeof(int32_t) * p->offs.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(p->d_offs, p->offs.data(), sizeof(int32_t) * p->offs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (fd && hipMemcpy(p->d_clsys, p->cl_sys.data(), sizeof(int32_t) * p->ncl, hipMemcpyHostToDevice) != hipSuccess)) {
     eq_plan_destroy(p);
     return EQ_EHIP;
   }
-  eq_status st = upload_tasks(p, p->tuned ? p->half : 0);
+  eq_status st = build_current(p);
   if (st != EQ_OK) {
     eq_plan_destroy(p);
     return st;
@@ -354,23 +525,21 @@ eq_status eq_plan_execute(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *
       ((uintptr_t)info % 4))
     return EQ_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (!p->tuned) {
+  if (!all_tuned(p)) {
     drop_graph(p);
     eq_status st = autotune(p, H, y, z, s2, info, s);
     if (st != EQ_OK) return st;
   }
-  eq_status st = upload_tasks(p, p->half);
+  eq_status st = build_current(p);
   if (st != EQ_OK) return st;
   const void *args[5] = {H, y, z, s2, info};
   bool same = p->exec != nullptr;
   for (int k = 0; k < 5 && same; ++k) same = args[k] == p->gargs[k];
   if (!same) {
     drop_graph(p);
-    if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) return EQ_EHIP;
-    // the captured launches must not run before the caller's prior work
-    RaggedArgs a = make_args(p, H, y, z, s2, info);
+    if (make_streams(p) != hipSuccess) return EQ_EHIP;
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed) != hipSuccess) return EQ_EHIP;
-    hipError_t e = enqueue(p, a, p->grid, p->cap);
+    hipError_t e = enqueue(p, p->wpc, true, H, y, z, s2, info, p->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -384,15 +553,21 @@ eq_status eq_plan_execute(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *
     }
     for (int k = 0; k < 5; ++k) p->gargs[k] = args[k];
   }
-  if (hipGraphLaunch(p->exec, s) != hipSuccess) return EQ_EHIP;
+  if (hipGraphLaunch(p->exec, s) != hipSuccess || hipEventRecord(p->done, s) != hipSuccess) return EQ_EHIP;
   return EQ_OK;
 }
 
-eq_status eq_plan_describe(const eq_plan *p, int32_t *out_waves, int32_t *out_tasks) {
+eq_status eq_plan_describe(const eq_plan *p, int32_t *out_shape, int32_t *out_tasks) {
   if (!p) return EQ_EINVAL;
-  if (out_waves) {
-    out_waves[0] = p->grid;
-    out_waves[1] = p->half;
+  if (out_shape) {
+    for (int c = 0; c < kClasses; ++c) {
+      int32_t *o = out_shape + 5 * c;
+      o[0] = p->n_sys[c];
+      o[1] = p->n_items[c];
+      o[2] = p->n_pieces[c];
+      o[3] = p->fd || refining(*p) ? 0 : p->piece_rows[c];
+      o[4] = grid_of(p, p->wpc);
+    }
   }
   if (out_tasks) *out_tasks = p->ntasks;
   return EQ_OK;
@@ -404,7 +579,9 @@ eq_status eq_plan_destroy(eq_plan *p) {
   // release everything, then report whether any release failed
   bool ok = true;
   if (p->cap) ok &= hipStreamDestroy(p->cap) == hipSuccess;
-  for (void *d : {(void *)p->d_sys, (void *)p->d_offs, (void *)p->d_tasks, (void *)p->d_order, (void *)p->d_scratch})
+  if (p->done) ok &= hipEventDestroy(p->done) == hipSuccess;
+  for (void *d : {(void *)p->d_sys, (void *)p->d_offs, (void *)p->d_clsys, (void *)p->d_tasks, (void *)p->d_order,
+                  (void *)p->d_scratch, (void *)p->d_part, (void *)p->d_fpart, (void *)p->d_fcode})
     if (d) ok &= hipFree(d) == hipSuccess;
   delete p;
   return ok ? EQ_OK : EQ_EHIP;

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert lib.eq_abi_version() == 2
+    assert lib.eq_abi_version() == 3
     for st, txt in api.STATUS.items():
         assert lib.eq_status_string(st).decode() == txt
 
@@ -342,3 +342,9 @@ def test_noalloc_validates_before_any_hip_call(lib):
     assert lib.eq_pd_noalloc(ct.byref(big), A, A, A, A, A, None) == ENOTSUP
     txt = open(HEADER).read()
     assert f"#define EQ_NOALLOC_MAX_W {api.NOALLOC_MAX_W}" in txt
+
+
+def test_plan_class_constants_match_header():
+    txt = open(HEADER).read()
+    assert f"#define EQ_PLAN_CLASSES {api.PLAN_CLASSES}" in txt
+    assert len(api.PLAN_CLASS_NAMES) == api.PLAN_CLASSES

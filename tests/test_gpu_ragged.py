@@ -1,6 +1,7 @@
 """Ragged batches (eq_plan_*): 4096 independent systems of uneven B_c, U, C
-in one persistent, graph-captured launch with autotuned launch shape; parity
-of every system against the FP64 oracle."""
+in one persistent, graph-captured launch with autotuned launch shape (waves
+per CU, PD piece rows per tile class); parity of every system against the
+FP64 oracle."""
 import json
 import os
 
@@ -58,14 +59,43 @@ def test_ragged_4096_fp32(rb, fd, tmp_path):
     print(f"ragged {'fd' if fd else 'pd'} fp32: z err {ez:.2e}, sigma2 {es:.4f} dB, {plan.describe()}", flush=True)
     assert ez <= TOL_Z["fp32"] and es <= TOL_DB
     assert np.all(host(info) == 0)
-    # the autotune cache holds this plan's launch shape; a second plan reuses it
+    # the autotune cache holds the launch entry (waves per CU) and, for PD,
+    # the piece rows of each tile class of the batch, keyed by device, mode,
+    # precision and class; a plan for another batch drawn from the same
+    # distribution takes its shape from the cache
+    mode = "fd" if fd else "pd"
     c = json.load(open(cache))
-    assert len(c) == 1
-    (entry,) = c.values()
     d = plan.describe()
-    assert entry["grid"] == d["grid"] and entry["half"] == d["half_items"]
+    assert sum(v["systems"] for v in d["classes"].values()) == rb.nsys
+    assert c[f"gfx950/{mode}/p0/launch"]["wpc"] in (4, 6, 8)
+    if fd:
+        assert len(c) == 1
+        assert sum(v["clusters"] for v in d["classes"].values()) == int(np.sum(rb.C))
+        assert all(v["piece_rows"] == 0 for v in d["classes"].values())
+    else:
+        assert len(c) == 1 + len(d["classes"])
+        for name, v in d["classes"].items():
+            assert c[f"gfx950/pd/p0/{name}"]["piece_rows"] == v["piece_rows"] in (0, 128, 256, 384, 512)
+    other = synth.make_ragged(4096, seed=synth.BASE_SEED + 99)
+    plan_o = api.Plan.from_ragged(other, fd=fd, precision="fp32", tune_cache=cache)
+    do = plan_o.describe()
+    wpc = c[f"gfx950/{mode}/p0/launch"]["wpc"]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert d["grid"] == min(cus * wpc, d["tasks"]) and do["grid"] == min(cus * wpc, do["tasks"])
+    for name, v in do["classes"].items():
+        if not fd:
+            assert c[f"gfx950/pd/p0/{name}"]["piece_rows"] == v["piece_rows"]
+    mtime = os.path.getmtime(cache)
+    zo, _, _ = plan_o.execute(dev(other.H_pool), dev(other.y_pool))
+    torch.cuda.synchronize()
+    assert os.path.getmtime(cache) == mtime  # no tuning run: everything was cached
+    zro, _ = oracle_ragged(other, fd, list(range(0, other.nsys, 11)))
+    zo_h = host(zo)
+    ez_o = max(float(np.max(np.abs(zo_h[int(other.z_off[k]):int(other.z_off[k]) + int(other.U[k])] - zk))
+                     / np.max(np.abs(zk))) for k, zk in zro.items())
+    assert ez_o <= TOL_Z["fp32"], ez_o
+    plan_o.close()
     plan2 = api.Plan.from_ragged(rb, fd=fd, precision="fp32", tune_cache=cache)
-    assert plan2.describe()["grid"] == d["grid"]
     # graph replays: same pools twice, then new pools (recapture)
     z1, _, _ = plan2.execute(H, y)
     z2, _, _ = plan2.execute(H, y)
@@ -73,6 +103,47 @@ def test_ragged_4096_fp32(rb, fd, tmp_path):
     z3, _, _ = plan2.execute(H2, y2)
     torch.cuda.synchronize()
     assert torch.equal(z1, z) and torch.equal(z2, z) and torch.equal(z3, z)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_ragged_pd_row_pieces(rb, prec, tmp_path):
+    """PD systems cut into row pieces of 32 rows (a cached shape): the
+    partial Grams of the pieces are summed by the system's last piece in
+    piece order, so every system matches the oracle, and two executions give
+    identical bits whichever wave finishes a system."""
+    from paper_1808_04473_amd import api
+    p = api.PRECISIONS[prec]
+    cache = tmp_path / "pieces.json"
+    cache.write_text("{\n"
+                     f'  "gfx950/pd/p{p}/launch": {{"wpc": 8}},\n'
+                     f'  "gfx950/pd/p{p}/ut16": {{"piece_rows": 32}},\n'
+                     f'  "gfx950/pd/p{p}/ut32": {{"piece_rows": 32}}\n'
+                     "}\n")
+    plan = api.Plan.from_ragged(rb, fd=False, precision=prec, tune_cache=cache)
+    d = plan.describe()
+    assert all(v["piece_rows"] == 32 for v in d["classes"].values())
+    # every system of more than 32 rows is cut (16-row blocks for UT = 32,
+    # 32-row blocks for UT = 16)
+    npieces = 0
+    for k in range(rb.nsys):
+        B, rpb = int(rb.B[k]), (32 if int(rb.U[k]) <= 16 else 16)
+        if B > 32:
+            nb = -(-B // rpb)
+            per = max(1, 32 // rpb)
+            npieces += -(-nb // per)
+    assert sum(v["pieces"] for v in d["classes"].values()) == npieces > 0
+    H, y = dev(rb.H_pool), dev(rb.y_pool)
+    z, s2, info = plan.execute(H, y)
+    z2, s22, _ = plan.execute(H, y, out=(torch.empty_like(z), torch.empty_like(s2), torch.empty_like(info)))
+    torch.cuda.synchronize()
+    assert torch.equal(z, z2) and torch.equal(s2, s22)
+    subset = list(range(0, rb.nsys, 5))
+    zr, sr = oracle_ragged(rb, False, subset)
+    ez, es = errors(rb, host(z), host(s2), zr, sr)
+    print(f"ragged pd {prec} pieces of 32 rows: z err {ez:.2e}, sigma2 {es:.4f} dB", flush=True)
+    assert ez <= TOL_Z[prec] and es <= TOL_DB
+    assert np.all(host(info) == 0)
+    plan.close()
 
 
 @pytest.mark.parametrize("fd", [False, True], ids=["pd", "fd"])
