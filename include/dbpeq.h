@@ -318,6 +318,20 @@ eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_shape, int32_t *out
    one of the releases failed. */
 eq_status eq_plan_destroy(eq_plan *plan);
 
+/* Measurement aid, not part of the equaliser: the device time of the main
+   kernel of the forward calls.  eq_kernel_timer_start creates `capacity`
+   pairs of HIP events (1 .. EQ_KERNEL_TIMER_MAX; EQ_EINVAL if the timer is
+   already on).  Until eq_kernel_timer_stop, each eq_pd / eq_fd /
+   eq_pd_noalloc call (any equaliser) records one pair on its stream, around
+   its Gram + solve (+ fusion) launch and without the FP64 re-solve launch,
+   while pairs remain; the calls allocate nothing for it.  eq_kernel_timer_stop
+   waits for the recorded events, writes the number of recorded pairs and the
+   sum of their elapsed times (ms), and destroys the events (EQ_EINVAL if the
+   timer is off).  Not for calls under stream capture. */
+#define EQ_KERNEL_TIMER_MAX 65536
+eq_status eq_kernel_timer_start(int32_t capacity);
+eq_status eq_kernel_timer_stop(int32_t *count, double *total_ms);
+
 const char *eq_status_string(eq_status s);
 int32_t eq_abi_version(void);
 

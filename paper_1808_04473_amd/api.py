@@ -81,6 +81,8 @@ SIGNATURES = [
     ("eq_plan_describe", c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     ("eq_plan_destroy", c_int32, [c_void_p]),
     ("eq_probe_read", c_int32, [c_void_p, c_size_t, c_void_p, c_void_p]),
+    ("eq_kernel_timer_start", c_int32, [c_int32]),
+    ("eq_kernel_timer_stop", c_int32, [POINTER(c_int32), POINTER(ctypes.c_double)]),
 ]
 
 
@@ -541,6 +543,33 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+KERNEL_TIMER_MAX = 65536  # EQ_KERNEL_TIMER_MAX
+
+
+class KernelTimer:
+    """Device time of the main kernel of the forward calls made inside the
+    `with` block (eq_kernel_timer_*): on exit, `count` launches were timed
+    and `mean_ms` is their average duration.  A measurement aid."""
+
+    def __init__(self, capacity):
+        self.capacity = int(capacity)
+        self.count, self.total_ms = 0, 0.0
+
+    def __enter__(self):
+        _check("eq_kernel_timer_start", load_library().eq_kernel_timer_start(self.capacity))
+        return self
+
+    def __exit__(self, *exc):
+        n, ms = c_int32(), ctypes.c_double()
+        _check("eq_kernel_timer_stop", load_library().eq_kernel_timer_stop(ctypes.byref(n), ctypes.byref(ms)))
+        self.count, self.total_ms = n.value, ms.value
+        return False
+
+    @property
+    def mean_ms(self):
+        return self.total_ms / self.count if self.count else float("nan")
 
 
 def probe_read(t, sink=None):

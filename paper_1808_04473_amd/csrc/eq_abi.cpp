@@ -3,11 +3,39 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "eq_common.h"
 
 using namespace dbpeq;
 
 namespace {
+
+// Measurement aid (eq_kernel_timer_*): pairs of events recorded around the
+// main kernel of the forward calls while the timer is on.
+struct KernelTimer {
+  std::mutex mu;
+  std::vector<hipEvent_t> ev;  // 2 per pair, created by eq_kernel_timer_start
+  size_t used = 0;             // pairs handed out
+  bool on = false;
+};
+
+KernelTimer &kernel_timer() {
+  static KernelTimer t;
+  return t;
+}
+
+// The next free pair, or two null events when the timer is off or full.
+void timer_pair(hipEvent_t &e0, hipEvent_t &e1) {
+  e0 = e1 = nullptr;
+  KernelTimer &t = kernel_timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on || 2 * (t.used + 1) > t.ev.size()) return;
+  e0 = t.ev[2 * t.used];
+  e1 = t.ev[2 * t.used + 1];
+  ++t.used;
+}
 
 constexpr size_t kWsHeader = 256;
 
@@ -100,11 +128,16 @@ eq_status forward_launch(const eq_problem *p, bool fd, const eq_c32 *H, const eq
   a.fb_count = reinterpret_cast<int32_t *>(ws);
   a.fb_done = a.fb_count + 1;
   a.fb_list = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + kWsHeader);
+  hipEvent_t e0, e1;
+  timer_pair(e0, e1);
+  if (e0 && hipEventRecord(e0, s) != hipSuccess) return EQ_EHIP;
   if (p->equalizer == EQ_MRC) {
     const int prec = p->precision == EQ_FP32 ? PREC_FP32 : PREC_BF16X3_NR;
-    return launch_mrc(a, fd, prec, s) == hipSuccess ? EQ_OK : EQ_EHIP;
+    if (launch_mrc(a, fd, prec, s) != hipSuccess) return EQ_EHIP;
+    return e1 && hipEventRecord(e1, s) != hipSuccess ? EQ_EHIP : EQ_OK;
   }
   if (launch_forward(a, fd, p->precision, s) != hipSuccess) return EQ_EHIP;
+  if (e1 && hipEventRecord(e1, s) != hipSuccess) return EQ_EHIP;
   if (launch_fp64_resolve(a, fd, s) != hipSuccess) return EQ_EHIP;
   return EQ_OK;
 }
@@ -313,6 +346,47 @@ eq_status eq_probe_read(const void *buf, size_t bytes, float *sink, void *stream
   if (!buf || !sink || !aligned(buf, 16) || !aligned(sink, 4) || bytes % 16 != 0) return EQ_EINVAL;
   if (launch_probe_read(buf, bytes, sink, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return EQ_EHIP;
   return EQ_OK;
+}
+
+eq_status eq_kernel_timer_start(int32_t capacity) {
+  if (capacity < 1 || capacity > EQ_KERNEL_TIMER_MAX) return EQ_EINVAL;
+  KernelTimer &t = kernel_timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (t.on) return EQ_EINVAL;
+  t.ev.assign(2 * (size_t)capacity, nullptr);
+  for (hipEvent_t &e : t.ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (hipEvent_t x : t.ev)
+        if (x) (void)hipEventDestroy(x);
+      t.ev.clear();
+      return EQ_EHIP;
+    }
+  }
+  t.used = 0;
+  t.on = true;
+  return EQ_OK;
+}
+
+eq_status eq_kernel_timer_stop(int32_t *count, double *total_ms) {
+  KernelTimer &t = kernel_timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on) return EQ_EINVAL;
+  t.on = false;
+  double sum = 0.0;
+  bool ok = true;
+  for (size_t k = 0; k < t.used && ok; ++k) {
+    float ms = 0.f;
+    ok = hipEventSynchronize(t.ev[2 * k + 1]) == hipSuccess &&
+         hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess;
+    sum += ms;
+  }
+  for (hipEvent_t e : t.ev)
+    if (e) ok &= hipEventDestroy(e) == hipSuccess;
+  if (count) *count = (int32_t)t.used;
+  if (total_ms) *total_ms = sum;
+  t.ev.clear();
+  t.used = 0;
+  return ok ? EQ_OK : EQ_EHIP;
 }
 
 const char *eq_status_string(eq_status s) {

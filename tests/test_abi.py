@@ -348,3 +348,15 @@ def test_plan_class_constants_match_header():
     txt = open(HEADER).read()
     assert f"#define EQ_PLAN_CLASSES {api.PLAN_CLASSES}" in txt
     assert len(api.PLAN_CLASS_NAMES) == api.PLAN_CLASSES
+
+
+def test_kernel_timer_argument_errors():
+    """The kernel timer refuses bad capacities and a stop without a start
+    before any HIP call (no device needed)."""
+    lib = api.load_library()
+    n, ms = ctypes.c_int32(), ctypes.c_double()
+    assert lib.eq_kernel_timer_start(0) == EINVAL
+    assert lib.eq_kernel_timer_start(api.KERNEL_TIMER_MAX + 1) == EINVAL
+    assert lib.eq_kernel_timer_stop(ctypes.byref(n), ctypes.byref(ms)) == EINVAL
+    txt = open(HEADER).read()
+    assert f"#define EQ_KERNEL_TIMER_MAX {api.KERNEL_TIMER_MAX}" in txt

@@ -240,3 +240,22 @@ def test_read_probe_runs():
     t = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
     assert api.probe_read(t) == 4 << 20
     torch.cuda.synchronize()
+
+
+def test_kernel_timer_times_each_forward_launch():
+    """The library's kernel timer records one event pair per forward call
+    (around the main kernel only) and leaves the results unchanged."""
+    from paper_1808_04473_amd import api
+    b = synth.config_batch(1, 10.0, W=256)
+    H, y = dev(b.H), dev(b.y)
+    z0, s0 = api.eq_pd(H, y, b.n0, b.cluster_off)
+    with api.KernelTimer(8) as kt:
+        for _ in range(5):
+            z1, s1 = api.eq_pd(H, y, b.n0, b.cluster_off)
+            z2, s2 = api.eq_fd(H, y, b.n0, b.cluster_off)
+    assert kt.count == 8 and kt.mean_ms > 0.0  # capacity 8: the last two calls are not timed
+    torch.cuda.synchronize()
+    assert torch.equal(z0, z1) and torch.equal(s0, s1)
+    with api.KernelTimer(4) as kt2:
+        pass
+    assert kt2.count == 0
