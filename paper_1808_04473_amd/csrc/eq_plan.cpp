@@ -116,7 +116,9 @@ eq_status build_items(eq_plan *p, const int (&rows)[kClasses]) {
         whole.push_back(k);
       }
     }
-    // rounds of up to 64/UT whole systems of equal U, largest first within a U
+    // rounds of up to 64/UT whole systems of equal U, largest first within a
+    // U; with pieces on, a round holds at most the class's piece rows (or its
+    // first system), so that no round streams much more than a piece
     std::stable_sort(whole.begin(), whole.end(), [&](int a, int b) {
       if (p->sys[a].U != p->sys[b].U) return p->sys[a].U < p->sys[b].U;
       return p->sys[a].B > p->sys[b].B;
@@ -125,9 +127,12 @@ eq_status build_items(eq_plan *p, const int (&rows)[kClasses]) {
     while (k < whole.size()) {
       const RSys &d = p->sys[whole[k]];
       const int per = 64 / d.ut;
-      int m = 0;
+      const int R = refining(*p) ? 0 : rows[cls_of(d.ut)];
+      int m = 0, nrows = 0;
       double cst = solve_cost(d.ut);
-      while (m < per && k + m < whole.size() && p->sys[whole[k + m]].U == d.U) {
+      while (m < per && k + m < whole.size() && p->sys[whole[k + m]].U == d.U &&
+             (m == 0 || R == 0 || nrows + p->sys[whole[k + m]].B <= R)) {
+        nrows += p->sys[whole[k + m]].B;
         cst += gram_cost(p->sys[whole[k + m]].B, d.ut);
         ++m;
       }
@@ -361,7 +366,7 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
   }
   for (int c = 0; c < kClasses; ++c) {
     if (p->tuned_rows[c] || p->fd || refining(*p) || p->n_sys[c] == 0) continue;
-    const int cand[] = {0, 128, 256, 384, 512};
+    const int cand[] = {0, 256, 384, 512, 768};
     float tbest = 1e30f;
     int best = p->piece_rows[c];
     for (int r : cand) {

@@ -75,7 +75,7 @@ def test_ragged_4096_fp32(rb, fd, tmp_path):
     else:
         assert len(c) == 1 + len(d["classes"])
         for name, v in d["classes"].items():
-            assert c[f"gfx950/pd/p0/{name}"]["piece_rows"] == v["piece_rows"] in (0, 128, 256, 384, 512)
+            assert c[f"gfx950/pd/p0/{name}"]["piece_rows"] == v["piece_rows"] in (0, 256, 384, 512, 768)
     other = synth.make_ragged(4096, seed=synth.BASE_SEED + 99)
     plan_o = api.Plan.from_ragged(other, fd=fd, precision="fp32", tune_cache=cache)
     do = plan_o.describe()
