@@ -587,45 +587,50 @@ struct Factor {
   float dinv;     // 1 / L_ii of this lane's row
 };
 
+// Step j of the right-looking Cholesky A = L L^H of the row held by each
+// lane: column j of L, then the update of the trailing columns j < k < KEND.
+template <int UT, int J, int KEND>
+__device__ __forceinline__ void chol_step(Factor<UT> &f, int i, int &fail) {
+  constexpr int j = J;
+  const float ajj = gbcast<UT, j>(f.a[j].x);
+  if (!(ajj > 0.f) && fail == 0) fail = j + 1;
+  // hardware reciprocal square root (about 1 ulp): 1/L_jj and L_jj = a_jj / sqrt(a_jj)
+  const float inv = __builtin_amdgcn_rsqf(ajj);
+  const float ljj = ajj * inv;
+  if (i == j) f.dinv = inv;
+  float2 lij = make_float2(f.a[j].x * inv, f.a[j].y * inv);
+  if (i == j) lij = make_float2(ljj, 0.f);
+  if (i < j) lij = make_float2(0.f, 0.f);
+  f.a[j] = lij;
+  const float2 lm = (i > j) ? lij : make_float2(0.f, 0.f);
+  // a_ik -= l_ij * conj(l_kj), with l_kj broadcast from lane k: the real
+  // part of l_kj for every k, then the imaginary part, so that no
+  // instruction reads an accumulator its predecessor wrote
+  const BSrc bx = bsrc<UT>(lij.x), by = bsrc<UT>(lij.y);
+  sfor<UT>([&](auto K) {
+    constexpr int k = K;
+    if constexpr (k > j && k < KEND) {
+      fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(bx), lm.x);
+      fmac_rowbcast<k % 16, true, 0>(f.a[k].y, bpick<k>(bx), lm.y);
+    }
+  });
+  sfor<UT>([&](auto K) {
+    constexpr int k = K;
+    if constexpr (k > j && k < KEND) {
+      fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(by), lm.y);
+      fmac_rowbcast<k % 16, false, 0>(f.a[k].y, bpick<k>(by), lm.x);
+    }
+  });
+  step_fence();
+}
+
 // Right-looking Cholesky A = L L^H of the row held by each lane.
 // Returns 0, or j+1 for the first pivot j that is not positive (or NaN).
 template <int UT>
 __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
   i = opaque_idx(i);
   int fail = 0;
-  sfor<UT>([&](auto J) {
-    constexpr int j = J;
-    const float ajj = gbcast<UT, j>(f.a[j].x);
-    if (!(ajj > 0.f) && fail == 0) fail = j + 1;
-    // hardware reciprocal square root (about 1 ulp): 1/L_jj and L_jj = a_jj / sqrt(a_jj)
-    const float inv = __builtin_amdgcn_rsqf(ajj);
-    const float ljj = ajj * inv;
-    if (i == j) f.dinv = inv;
-    float2 lij = make_float2(f.a[j].x * inv, f.a[j].y * inv);
-    if (i == j) lij = make_float2(ljj, 0.f);
-    if (i < j) lij = make_float2(0.f, 0.f);
-    f.a[j] = lij;
-    const float2 lm = (i > j) ? lij : make_float2(0.f, 0.f);
-    // a_ik -= l_ij * conj(l_kj), with l_kj broadcast from lane k: the real
-    // part of l_kj for every k, then the imaginary part, so that no
-    // instruction reads an accumulator its predecessor wrote
-    const BSrc bx = bsrc<UT>(lij.x), by = bsrc<UT>(lij.y);
-    sfor<UT>([&](auto K) {
-      constexpr int k = K;
-      if constexpr (k > j) {
-        fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(bx), lm.x);
-        fmac_rowbcast<k % 16, true, 0>(f.a[k].y, bpick<k>(bx), lm.y);
-      }
-    });
-    sfor<UT>([&](auto K) {
-      constexpr int k = K;
-      if constexpr (k > j) {
-        fmac_rowbcast<k % 16, true, k == j + 1 ? 4 : 0>(f.a[k].x, bpick<k>(by), lm.y);
-        fmac_rowbcast<k % 16, false, 0>(f.a[k].y, bpick<k>(by), lm.x);
-      }
-    });
-    step_fence();
-  });
+  sfor<UT>([&](auto J) { chol_step<UT, J, UT>(f, i, fail); });
   return fail;
 }
 
@@ -633,33 +638,161 @@ __device__ __forceinline__ int cholesky(Factor<UT> &f, int i) {
 //   X_ju = (delta_ju - sum_{k<j} L_jk X_ku) / L_jj,
 // right-looking: once X_ju is final, every later row i subtracts L_ij X_ju
 // (L_ij broadcast from lane i), so each step has UT - 1 - j independent
-// accumulators instead of one long chain.
+// accumulators instead of one long chain.  inv_step is step j, with the
+// update restricted to the rows j < i < IEND.
+template <int UT, int J, int IEND>
+__device__ __forceinline__ void inv_step(Factor<UT> &f) {
+  constexpr int j = J;
+  const float invj = gbcast<UT, j>(f.dinv);
+  f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
+  // x_i -= L_ij x_j: real part of L_ij for every i, then the imaginary part
+  const BSrc bx = bsrc<UT>(f.a[j].x), by = bsrc<UT>(f.a[j].y);
+  sfor<UT>([&](auto I) {
+    constexpr int i = I;
+    if constexpr (i > j && i < IEND) {
+      fmac_rowbcast<i % 16, true, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(bx), f.x[j].x);
+      fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(bx), f.x[j].y);
+    }
+  });
+  sfor<UT>([&](auto I) {
+    constexpr int i = I;
+    if constexpr (i > j && i < IEND) {
+      fmac_rowbcast<i % 16, false, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(by), f.x[j].y);
+      fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(by), f.x[j].x);
+    }
+  });
+  step_fence();
+}
+
 template <int UT>
 __device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
   u = opaque_idx(u);
 #pragma unroll
   for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
-  sfor<UT>([&](auto J) {
+  sfor<UT>([&](auto J) { inv_step<UT, J, UT>(f); });
+}
+
+// ---- 32 x 32: the two 16 x 16 x 16 products of the blocked forms on MFMA
+// With A = [A11 A12; A21 A22] in 16 x 16 blocks, the Cholesky factor is
+// L11 = chol(A11), L21 = A21 L11^{-H}, L22 = chol(A22 - L21 L21^H), and the
+// inverse X = L^{-1} has X11 = L11^{-1}, X22 = L22^{-1}, X21 = -X22 (L21 X11).
+// The first 16 steps of the factorisation and of the inverse run on their
+// own block only; the Schur complement A22 - L21 L21^H and -L21 X11 are
+// complex products on 16x16x4 FP32 MFMA, staged through the LDS matrix slot
+// of each system of the wave (free while the solve runs), and the last 16
+// steps are the usual ones.  This moves 2,048 of the DPP FMACs of a round
+// onto the matrix cores.  Each slot holds three 16 x 16 matrices with a row
+// stride of 17 elements (a column read touches 16 distinct bank pairs):
+// L21 at 0, A22 / S then X11 at kSplitM, -L21 X11 at kSplitY.
+constexpr int kSplitStride = 17;
+constexpr int kSplitM = 16 * kSplitStride;
+constexpr int kSplitY = 32 * kSplitStride;
+
+// C (16 x 16, MFMA D layout) += sign(A) * A B over K = 16 for complex A, B
+// given per lane as A[lr][4 kc + lg] and B[4 kc + lg][lr] (lr = lane % 16,
+// lg = lane / 16): the four real products of the complex one.
+template <class GetA, class GetB>
+__device__ __forceinline__ void cmma16(f4 &re, f4 &im, GetA ga, GetB gb, bool neg) {
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const float2 p = ga(kc), q = gb(kc);
+    const float s = neg ? -1.f : 1.f;
+    re = mma32(s * p.x, q.x, re);
+    re = mma32(-s * p.y, q.y, re);
+    im = mma32(s * p.x, q.y, im);
+    im = mma32(s * p.y, q.x, im);
+  }
+}
+
+// Schur complement of the 32 x 32 systems of the wave: lanes 16..31 of each
+// group (rows 16..31) hold L21 in a[0..15] and A22 in a[16..31] on entry and
+// S = A22 - L21 L21^H in a[16..31] on return.  base: the wave's LDS slots.
+__device__ __forceinline__ void schur32_mfma(Factor<32> &f, int gi, float2 *base) {
+  const int lane = lane_id();
+  float2 *W = base + (lane / 32) * 1024;
+  if (gi >= 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      W[(gi - 16) * kSplitStride + k] = f.a[k];
+      W[kSplitM + (gi - 16) * kSplitStride + k] = f.a[16 + k];
+    }
+  }
+  __syncthreads();
+  const int lr = lane % 16, lg = lane / 16;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float2 *Ws = base + s * 1024;
+    f4 re, im;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float2 v = Ws[kSplitM + (4 * lg + r) * kSplitStride + lr];
+      re[r] = v.x;
+      im[r] = v.y;
+    }
+    // (L21 L21^H)[i][j] = sum_k L21[i][k] conj(L21[j][k]): both operands are
+    // the element (lr, 4 kc + lg) of L21
+    auto ga = [&](int kc) { return Ws[lr * kSplitStride + 4 * kc + lg]; };
+    auto gb = [&](int kc) {
+      const float2 v = Ws[lr * kSplitStride + 4 * kc + lg];
+      return make_float2(v.x, -v.y);
+    };
+    cmma16(re, im, ga, gb, true);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ws[kSplitM + (4 * lg + r) * kSplitStride + lr] = make_float2(re[r], im[r]);
+  }
+  __syncthreads();
+  if (gi >= 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f.a[16 + k] = W[kSplitM + (gi - 16) * kSplitStride + k];
+  }
+}
+
+__device__ __forceinline__ int cholesky32_split(Factor<32> &f, int i, float2 *base) {
+  i = opaque_idx(i);
+  int fail = 0;
+  sfor<16>([&](auto J) { chol_step<32, J, 16>(f, i, fail); });
+  schur32_mfma(f, i, base);
+  sfor<16>([&](auto J) {
     constexpr int j = J;
-    const float invj = gbcast<UT, j>(f.dinv);
-    f.x[j] = make_float2(f.x[j].x * invj, f.x[j].y * invj);
-    // x_i -= L_ij x_j: real part of L_ij for every i, then the imaginary part
-    const BSrc bx = bsrc<UT>(f.a[j].x), by = bsrc<UT>(f.a[j].y);
-    sfor<UT>([&](auto I) {
-      constexpr int i = I;
-      if constexpr (i > j) {
-        fmac_rowbcast<i % 16, true, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(bx), f.x[j].x);
-        fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(bx), f.x[j].y);
-      }
-    });
-    sfor<UT>([&](auto I) {
-      constexpr int i = I;
-      if constexpr (i > j) {
-        fmac_rowbcast<i % 16, false, i == j + 1 ? 4 : 0>(f.x[i].x, bpick<i>(by), f.x[j].y);
-        fmac_rowbcast<i % 16, true, 0>(f.x[i].y, bpick<i>(by), f.x[j].x);
-      }
-    });
-    step_fence();
+    chol_step<32, j + 16, 32>(f, i, fail);
+  });
+  return fail;
+}
+
+// X = L^{-1} by columns (lane u = column u), with rows 16..31 of the columns
+// u < 16 set to -L21 X11 on MFMA between the two halves.  L21 is still in
+// each slot from cholesky32_split.
+__device__ __forceinline__ void inverse32_split(Factor<32> &f, int u, float2 *base) {
+  u = opaque_idx(u);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+  sfor<16>([&](auto J) { inv_step<32, J, 16>(f); });
+  const int lane = lane_id();
+  float2 *W = base + (lane / 32) * 1024;
+  if (u < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) W[kSplitM + k * kSplitStride + u] = f.x[k];
+  }
+  __syncthreads();
+  const int lr = lane % 16, lg = lane / 16;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float2 *Ws = base + s * 1024;
+    f4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+    auto ga = [&](int kc) { return Ws[lr * kSplitStride + 4 * kc + lg]; };
+    auto gb = [&](int kc) { return Ws[kSplitM + (4 * kc + lg) * kSplitStride + lr]; };
+    cmma16(re, im, ga, gb, true);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ws[kSplitY + (4 * lg + r) * kSplitStride + lr] = make_float2(re[r], im[r]);
+  }
+  __syncthreads();
+  if (u < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f.x[16 + k] = W[kSplitY + k * kSplitStride + u];
+  }
+  sfor<16>([&](auto J) {
+    constexpr int j = J;
+    inv_step<32, j + 16, 32>(f);
   });
 }
 
@@ -734,7 +867,17 @@ __device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
 // 32-lane groups store L there and form the inverse from LDS.
 template <int UT>
 __device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail,
-                                               float2 (*Ls)[UT] = nullptr) {
+                                               float2 (*Ls)[UT] = nullptr, float2 *split = nullptr) {
+  if constexpr (UT == 32) {
+    if (split) {
+      // the wave's systems each own an LDS matrix slot (split: the first)
+      fail = cholesky32_split(f, i, split);
+      const float2 t = fwd_subst<UT>(f, i, m);
+      asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));
+      inverse32_split(f, i, split);
+      return apply_xh<UT>(f, t);
+    }
+  }
   fail = cholesky<UT>(f, i);
   const float2 t = fwd_subst<UT>(f, i, m);
   asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));

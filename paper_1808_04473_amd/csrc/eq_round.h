@@ -53,7 +53,11 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, 
   r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
   // with fewer slots than groups (PD items of one 32-lane system) the freed
   // registers raise occupancy, so the inverse reads L from LDS there
-  r.z = factor_solve<UT>(r.f, i, m, r.fail, SM::NS < SM::NSYS ? sm.A[sme] : nullptr);
+  // with a slot per system, the 32 x 32 forms run their two block products
+  // on MFMA through the slots (read above, free until the solve ends)
+  float2 *split = nullptr;
+  if constexpr (UT == 32 && SM::NS == SM::NSYS) split = &sm.A[0][0][0];
+  r.z = factor_solve<UT>(r.f, i, m, r.fail, SM::NS < SM::NSYS ? sm.A[sme] : nullptr, split);
   r.d = inv_diag<UT>(r.f);
 }
 
