@@ -898,7 +898,16 @@ __device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, i
 // Returns 0 or the first bad pivot + 1.  With Ls (32-lane groups) L is
 // stored there and the inverse is formed from LDS, as in factor_solve.
 template <int UT>
-__device__ __forceinline__ int factor_inverse(Factor<UT> &f, int i, float2 (*Ls)[UT] = nullptr) {
+__device__ __forceinline__ int factor_inverse(Factor<UT> &f, int i, float2 (*Ls)[UT] = nullptr,
+                                              float2 *split = nullptr) {
+  if constexpr (UT == 32) {
+    if (split) {
+      // the wave's systems each own an LDS matrix slot (split: the first)
+      const int fail = cholesky32_split(f, i, split);
+      inverse32_split(f, i, split);
+      return fail;
+    }
+  }
   const int fail = cholesky<UT>(f, i);
   if (UT == 32 && Ls) {
 #pragma unroll

@@ -268,7 +268,12 @@ __device__ __forceinline__ void sym_factor(SymSolve<UT> &r, SM &sm, int slot, in
   }
   r.bad = gany<UT>(bad);
   r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
-  r.fail = factor_inverse<UT>(r.f, i, SM::NS < SM::NSYS ? sm.A[slot] : nullptr);
+  // with a slot per system, the 32 x 32 factor and inverse run their two
+  // block products on MFMA through the slots (read above, free until X is
+  // parked)
+  float2 *split = nullptr;
+  if constexpr (UT == 32 && SM::NS == SM::NSYS) split = &sm.A[0][0][0];
+  r.fail = factor_inverse<UT>(r.f, i, SM::NS < SM::NSYS ? sm.A[slot] : nullptr, split);
   r.d = inv_diag<UT>(r.f);
   __syncthreads();
   // row u of the slot holds column u of X: lds_el(A, u, k) = X_ku
