@@ -298,9 +298,9 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *host_desc, int32_t nsys,
    ([nsys], may be NULL).  The first call on a plan autotunes what the cache
    has no entry for (timing the launch on these pools, which it overwrites
    as a normal call would) and captures the launch into a hipGraph; later
-   calls with the same pools replay the graph.  Stream-ordered, except that a call
-   with other pools first waits for the plan's previous launch to finish (on
-   the host) before it replaces the graph. */
+   calls with the same pools replay the graph.  Stream-ordered, except that
+   a call with other pools first waits on the host for the plan's previous
+   launch to finish before it replaces the graph. */
 eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypool,
                           eq_c32 *zpool, float *s2pool, int32_t *info, void *stream);
 
@@ -314,8 +314,9 @@ eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypoo
 eq_status eq_plan_describe(const eq_plan *plan, int32_t *out_shape, int32_t *out_tasks);
 
 /* Waits on the host for the plan's last launch, then frees the plan and
-   every device buffer, stream and graph it holds (a null plan is a no-op).  The plan is gone on return either way; EQ_EHIP reports that
-   one of the releases failed. */
+   every device buffer, stream and graph it holds (a null plan is a no-op).
+   The plan is gone on return either way; EQ_EHIP reports that one of the
+   releases failed. */
 eq_status eq_plan_destroy(eq_plan *plan);
 
 /* Measurement aid, not part of the equaliser: the device time of the main
@@ -327,7 +328,8 @@ eq_status eq_plan_destroy(eq_plan *plan);
    while pairs remain; the calls allocate nothing for it.  eq_kernel_timer_stop
    waits for the recorded events, writes the number of recorded pairs and the
    sum of their elapsed times (ms), and destroys the events (EQ_EINVAL if the
-   timer is off).  Not for calls under stream capture. */
+   timer is off).  Not for calls under stream capture, and start / stop must
+   not overlap forward calls made on other host threads. */
 #define EQ_KERNEL_TIMER_MAX 65536
 eq_status eq_kernel_timer_start(int32_t capacity);
 eq_status eq_kernel_timer_stop(int32_t *count, double *total_ms);

@@ -1,8 +1,8 @@
 // Persistent kernel for ragged batches.  Each wave takes work items from its
-// queue's atomic head until that queue is empty (every wave reaches the
-// exit).
-// Items are cost-sorted on the host (largest first), so the tail of the
-// launch is made of the cheapest ones.  The per-item work is the fused Gram +
+// queue's atomic head (eight queues, the items dealt round-robin) until that
+// queue is empty; every wave reaches the exit.  Items are cost-sorted on the
+// host (largest first), so the tail of the launch is made of the cheapest
+// ones.  The per-item work is the fused Gram +
 // solve (+ fusion) of the uniform kernels, with every system's shape, N0 and
 // cluster offsets read from the descriptor table.  Three kinds of item:
 //
