@@ -184,3 +184,66 @@ def test_ragged_small_mixed_and_ill_conditioned(tmp_path):
         zr, sr = oracle_ragged(rb, fd)
         ez, es = errors(rb, host(z), host(s2), zr, sr)
         assert ez <= 1e-4 and es <= TOL_DB
+
+
+def _custom_batch(specs, seed=11):
+    """A ragged batch of the given systems: specs = [(U, [cluster sizes])],
+    i.i.d. Rayleigh H, 16-QAM symbols, SNR 10 dB."""
+    rng = np.random.default_rng(seed)
+    pts = synth.constellation("16qam")
+    Us = np.array([u for u, _ in specs], np.int64)
+    Cs = np.array([len(c) for _, c in specs], np.int64)
+    Bs = np.array([int(sum(c)) for _, c in specs], np.int64)
+    h_off = np.concatenate([[0], np.cumsum(Bs * Us)[:-1]]).astype(np.int64)
+    y_off = np.concatenate([[0], np.cumsum(Bs)[:-1]]).astype(np.int64)
+    z_off = np.concatenate([[0], np.cumsum(Us)[:-1]]).astype(np.int64)
+    clus_first = np.concatenate([[0], np.cumsum(Cs)[:-1]]).astype(np.int64)
+    H_pool = np.empty(int((Bs * Us).sum()), np.complex64)
+    y_pool = np.empty(int(Bs.sum()), np.complex64)
+    n0 = np.empty(len(specs), np.float32)
+    for k in range(len(specs)):
+        B, U = int(Bs[k]), int(Us[k])
+        H = (rng.standard_normal((B, U)) + 1j * rng.standard_normal((B, U))) / np.sqrt(2 * B)
+        s = pts[rng.integers(0, len(pts), size=U)]
+        n0[k] = synth.noise_variance(U, B, 10.0)
+        y = H @ s + (rng.standard_normal(B) + 1j * rng.standard_normal(B)) * np.sqrt(n0[k] / 2)
+        H_pool[h_off[k]:h_off[k] + B * U] = H.reshape(-1).astype(np.complex64)
+        y_pool[y_off[k]:y_off[k] + B] = y.astype(np.complex64)
+    return synth.RaggedBatch(H_pool=H_pool, y_pool=y_pool, s_pool=np.zeros(int(Us.sum()), np.complex64),
+                             B=Bs.astype(np.int32), U=Us.astype(np.int32), C=Cs.astype(np.int32), n0=n0,
+                             h_off=h_off, y_off=y_off, z_off=z_off, clus_first=clus_first,
+                             cluster_sizes=np.concatenate([np.array(c, np.int32) for _, c in specs]))
+
+
+EXTREME = [
+    (8, [40]), (16, [64]), (24, [48]), (32, [96]),         # FD with one cluster
+    (8, [16] * 64), (16, [32] * 40), (32, [40] * 24),      # clusters over many rounds
+    (1, [3, 5]), (17, [20, 18, 30]), (2, [1, 1, 1]),       # U = 1, 17, one-row clusters
+    (32, [64] * 60), (16, [256] * 4),                      # B = 3840 and 1024: many pieces
+]
+
+
+@pytest.mark.parametrize("fd", [False, True], ids=["pd", "fd"])
+@pytest.mark.parametrize("rows", [None, 32], ids=["tuned", "pieces32"])
+def test_ragged_extreme_shapes(fd, rows, tmp_path):
+    """Single-cluster FD systems, systems whose 24-64 clusters span many
+    rounds, U = 1 and 17, one-row clusters, and systems cut into up to 120
+    row pieces: every system against the oracle."""
+    from paper_1808_04473_amd import api
+    rb = _custom_batch(EXTREME)
+    cache = tmp_path / "t.json"
+    if rows is not None:
+        mode = "fd" if fd else "pd"
+        cache.write_text("{\n" + f'  "gfx950/{mode}/p0/launch": {{"wpc": 8}},\n'
+                         f'  "gfx950/{mode}/p0/ut16": {{"piece_rows": {rows}}},\n'
+                         f'  "gfx950/{mode}/p0/ut32": {{"piece_rows": {rows}}}\n' + "}\n")
+    plan = api.Plan.from_ragged(rb, fd=fd, precision="fp32", tune_cache=cache)
+    z, s2, info = plan.execute(dev(rb.H_pool), dev(rb.y_pool))
+    torch.cuda.synchronize()
+    zr, sr = oracle_ragged(rb, fd)
+    ez, es = errors(rb, host(z), host(s2), zr, sr)
+    print(f"ragged extreme {'fd' if fd else 'pd'} rows={rows}: z err {ez:.2e}, sigma2 {es:.4f} dB, "
+          f"{plan.describe()}", flush=True)
+    assert ez <= 1e-4 and es <= TOL_DB
+    assert np.all((host(info) & ~(1 << 30)) == 0)
+    plan.close()
