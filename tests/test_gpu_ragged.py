@@ -177,13 +177,18 @@ def test_ragged_small_mixed_and_ill_conditioned(tmp_path):
     rb.n0[k] = np.float32(1e-9)
     for fd in (False, True):
         plan = api.Plan.from_ragged(rb, fd=fd, precision="fp32", tune_cache=tmp_path / "t.json")
-        z, s2, info = plan.execute(dev(rb.H_pool), dev(rb.y_pool))
-        torch.cuda.synchronize()
-        info = host(info)
-        assert (info[k] & (1 << 30)) != 0
+        Hd, yd = dev(rb.H_pool), dev(rb.y_pool)
         zr, sr = oracle_ragged(rb, fd)
-        ez, es = errors(rb, host(z), host(s2), zr, sr)
-        assert ez <= 1e-4 and es <= TOL_DB
+        # three executions of the captured graph: the queue heads, arrival
+        # counters and FP64 queue must start each execution at zero
+        for rep in range(3):
+            z, s2, info = plan.execute(Hd, yd)
+            torch.cuda.synchronize()
+            info = host(info)
+            assert (info[k] & (1 << 30)) != 0
+            assert np.all((info & ~(1 << 30)) == 0)
+            ez, es = errors(rb, host(z), host(s2), zr, sr)
+            assert ez <= 1e-4 and es <= TOL_DB, rep
 
 
 def _custom_batch(specs, seed=11):
