@@ -300,7 +300,9 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *host_desc, int32_t nsys,
    as a normal call would) and captures the launch into a hipGraph; later
    calls with the same pools replay the graph.  Stream-ordered, except that
    a call with other pools first waits on the host for the plan's previous
-   launch to finish before it replaces the graph. */
+   launch to finish before it replaces the graph.  Calls on one plan share
+   its queue counters and slots (each call leaves them as the next expects),
+   so calls on different streams must be ordered by the caller. */
 eq_status eq_plan_execute(eq_plan *plan, const eq_c32 *Hpool, const eq_c32 *ypool,
                           eq_c32 *zpool, float *s2pool, int32_t *info, void *stream);
 

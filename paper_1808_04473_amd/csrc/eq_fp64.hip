@@ -223,10 +223,15 @@ __global__ __launch_bounds__(64) void eq_fp64_kernel(const FwdArgs a) {
   }
 }
 
+// The ragged form runs after the persistent launch, so it also clears that
+// launch's queue heads for the next execution; its own count is cleared as
+// in eq_fp64_kernel.
 template <bool FD>
 __global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) {
   __shared__ F64Smem sm;
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.counter[threadIdx.x * kQueueStride] = 0;
   const int n = min(*a.fb_count, a.nsys);
+  if ((int)blockIdx.x >= n) return;
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int k = a.fb_list[q];
     if (k < 0 || k >= a.nsys) continue;
@@ -240,6 +245,14 @@ __global__ __launch_bounds__(64) void eq_fp64_ragged_kernel(const RaggedArgs a) 
                 (double)d.n0 / (double)a.es, 0.0, FD, nullptr, a.zpool + d.z_off,
                 a.s2pool ? a.s2pool + d.z_off : nullptr, info, 1, 0, 0);
     if (threadIdx.x == 0 && a.info) a.info[k] = worst | EQ_INFO_FP64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // every block read the count before it arrives here
+    if (atomicAdd(a.fb_done, 1) == min(n, (int)gridDim.x) - 1) {
+      *a.fb_count = 0;
+      *a.fb_done = 0;
+    }
   }
 }
 

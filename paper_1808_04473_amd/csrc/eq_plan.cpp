@@ -51,7 +51,7 @@ struct eq_plan {
   int32_t *d_clsys = nullptr;
   RTask *d_tasks = nullptr;
   int32_t *d_order = nullptr;
-  int32_t *d_scratch = nullptr;  // [0, kHeads) queue heads, [kHeads] FP64 count,
+  int32_t *d_scratch = nullptr;  // [0, kHeads) queue heads, [kHeads] FP64 count, [kHeads + 1] FP64 blocks done,
                                  // [kList, kList + nsys) FP64 list, [kList + nsys, kList + 2 nsys) arrivals
   float *d_part = nullptr;       // PD partial slots
   float *d_fpart = nullptr;      // FD fusion terms
@@ -280,6 +280,7 @@ RaggedArgs make_args(const eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 
   a.cl_sys = p->d_clsys;
   a.counter = p->d_scratch;
   a.fb_count = p->d_scratch + kHeads;
+  a.fb_done = p->d_scratch + kHeads + 1;
   a.fb_list = p->d_scratch + kList;
   a.arrive = p->d_scratch + kList + p->nsys;
   a.part = p->d_part;
@@ -298,12 +299,20 @@ int grid_of(const eq_plan *p, int wpc) {
   return std::max(1, std::max(g, std::min(kQueues, p->ntasks)));
 }
 
-// Clears the queue heads, the FP64 count and the arrival counters, runs the
-// persistent launch, then (fp64) the FP64 re-solve of the systems it queued.
+// Queue heads, FP64 count and arrival counters to zero.
+hipError_t clear_scratch(const eq_plan *p, hipStream_t s) {
+  return launch_zero_i32(p->d_scratch, kList + 2 * p->nsys, s);
+}
+
+// Runs the persistent launch, then (fp64) the FP64 re-solve of the systems it
+// queued.  With fp64 the scratch is left at zero for the next execution
+// (finishers reset their arrival counters, the FP64 launch the queue heads
+// and its count); without it (autotuning) the scratch is cleared first, and
+// clear_scratch must run once more before the next fp64 execution.
 hipError_t enqueue(const eq_plan *p, int wpc, bool fp64, const eq_c32 *H, const eq_c32 *y, eq_c32 *z,
                    float *s2, int32_t *info, hipStream_t s) {
-  hipError_t e = launch_zero_i32(p->d_scratch, kList + 2 * p->nsys, s);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!fp64 && (e = clear_scratch(p, s)) != hipSuccess) return e;
   const RaggedArgs a = make_args(p, H, y, z, s2, info);
   if ((e = launch_ragged(a, p->fd != 0, p->prec, grid_of(p, wpc), s)) != hipSuccess) return e;
   return fp64 ? launch_fp64_ragged(a, p->fd != 0, s) : hipSuccess;
@@ -384,6 +393,8 @@ eq_status autotune(eq_plan *p, const eq_c32 *H, const eq_c32 *y, eq_c32 *z, floa
     m[key_rows(*p, c)] = best;
   }
   write_cache(p->cache_path, m);
+  // the timed launches ran without the FP64 launch that clears the scratch
+  if (clear_scratch(p, s) != hipSuccess) return EQ_EHIP;
   return build_current(p);
 }
 
@@ -509,7 +520,11 @@ eq_status eq_plan_create(eq_plan **out, const eq_sys *desc, int32_t nsys, const 
     eq_plan_destroy(p);
     return EQ_ENOMEM;
   }
-  if (hipMemcpy(p->d_offs, p->offs.data(), sizeof(int32_t) * p->offs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+  // executions start from zeroed scratch and leave it so (enqueue); the wait
+  // covers callers whose stream does not wait on the null stream
+  if (hipMemset(p->d_scratch, 0, sizeof(int32_t) * (kList + 2 * (size_t)nsys)) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess ||
+      hipMemcpy(p->d_offs, p->offs.data(), sizeof(int32_t) * p->offs.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (fd && hipMemcpy(p->d_clsys, p->cl_sys.data(), sizeof(int32_t) * p->ncl, hipMemcpyHostToDevice) != hipSuccess)) {
     eq_plan_destroy(p);
     return EQ_EHIP;

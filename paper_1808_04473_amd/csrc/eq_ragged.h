@@ -54,10 +54,14 @@ struct RaggedArgs {
   const RTask *tasks;
   const int32_t *order;   // systems of group items, then clusters of round items
   const int32_t *cl_sys;  // system of each global cluster (FD)
-  int32_t *counter;       // work-queue heads, kQueueStride apart (cleared before every execution)
+  // An execution leaves these at zero for the next one: each system's
+  // finisher resets its arrival counter, and the FP64 launch that follows the
+  // persistent one clears the queue heads and then its own queue.
+  int32_t *counter;       // work-queue heads, kQueueStride apart
   int32_t *fb_count;      // FP64 re-solve queue
+  int32_t *fb_done;       // FP64 blocks done
   int32_t *fb_list;
-  int32_t *arrive;        // per system: pieces (PD) or clusters (FD) finished (cleared before every execution)
+  int32_t *arrive;        // per system: pieces (PD) or clusters (FD) finished
   float *part;            // PD partial accumulators, kPartStride floats per slot
   float *fpart;           // FD fusion terms, kFusionStride x 4 floats per cluster
   int32_t *fcode;         // FD per cluster: failure code, routed to FP64

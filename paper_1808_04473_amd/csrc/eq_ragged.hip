@@ -138,6 +138,8 @@ __device__ __forceinline__ void pd_piece(const RaggedArgs &a, const RTask &task,
   if (lane == 0) old = atomicAdd(a.arrive + k, 1);
   old = __shfl(old, 0);
   if (old != np - 1) return;
+  // every piece has arrived: the counter starts the next execution at zero
+  if (lane == 0) a.arrive[k] = 0;
   // the last piece: sum every piece's slot in piece order, then solve alone
   Acc<UT> acc;
   acc_zero<UT>(acc);
@@ -226,6 +228,8 @@ __device__ __forceinline__ void fd_round(const RaggedArgs &a, const RTask &task,
   old = __shfl(old, sme * UT);
   const bool fin = live && old == a.sys[k].C - 1;
   if (__ballot(fin) == 0ull) return;
+  // every cluster has arrived: the counter starts the next execution at zero
+  if (fin && i == 0) a.arrive[k] = 0;
   // groups that finished their system's last cluster fuse its C clusters in
   // cluster order
   if (fin) {
