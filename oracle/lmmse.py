@@ -78,9 +78,12 @@ def lmmse_error_variance_simplified(G, n0, es=1.0):
 
 def cond_estimate(A):
     """Upper bound on the 2-norm condition number of an HPD matrix A:
-    ||A||_1 * trace(A^{-1}) >= lambda_max / lambda_min."""
+    ||A||_1 * trace(A^{-1}) >= lambda_max / lambda_min, with the 1-norm's
+    entry moduli replaced by |Re| + |Im| (at most sqrt(2) larger, so still a
+    bound; this is the routing estimate of the FP64 re-solve, which is not
+    part of the paper)."""
     A = _c128(A)
-    n1 = np.max(np.sum(np.abs(A), axis=-2), axis=-1)
+    n1 = np.max(np.sum(np.abs(A.real) + np.abs(A.imag), axis=-2), axis=-1)
     tr = np.real(np.trace(np.linalg.inv(A), axis1=-2, axis2=-1))
     return n1 * tr
 

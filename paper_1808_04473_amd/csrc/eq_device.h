@@ -937,6 +937,16 @@ __device__ __forceinline__ float inv_diag(const Factor<UT> &f) {
 
 __device__ __forceinline__ bool finite2(float2 v) { return isfinite(v.x) && isfinite(v.y); }
 
+// Row sums for the condition estimate and the finiteness test of a system:
+// (|Re| + |Im|) of each entry, scaled by 2^-32 so that no row of finite
+// entries overflows.  The scaled sum is finite exactly when every entry is,
+// and 2^32 times it bounds the row's sum of moduli from above (by at most
+// sqrt 2).  Two FMAs per entry, against a square root and two compares.
+constexpr float kRowScale = 0x1p-32f;
+__device__ __forceinline__ float abs_row_acc(float acc, float2 v) {
+  return fmaf(fabsf(v.y), kRowScale, fmaf(fabsf(v.x), kRowScale, acc));
+}
+
 // Unbiased L-MMSE: the L-MMSE estimate of user u has gain
 // mu_u = [(G + rho I)^{-1} G]_uu = 1 - rho d_u = 1 - sigma2_u / E_s; returns
 // 1 / mu_u for ub = 1/E_s, and exactly 1 for ub = 0 (biased L-MMSE, ZF).

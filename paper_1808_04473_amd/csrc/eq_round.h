@@ -39,18 +39,15 @@ struct LocalSolve {
 
 template <int UT, class SM>
 __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, int i, int U) {
-  bool bad = false;
   float rowsum = 0.f;
 #pragma unroll
   for (int k = 0; k < UT; ++k) {
     r.f.a[k] = lds_el<UT>(sm.A[sme], i, k);
-    bad |= !finite2(r.f.a[k]);
-    rowsum += __builtin_amdgcn_sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
+    rowsum = abs_row_acc(rowsum, r.f.a[k]);
   }
   const float2 m = sm.M[sme][i];
-  bad |= !finite2(m);
-  r.bad = gany<UT>(bad);
-  r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
+  r.bad = gany<UT>(!isfinite(abs_row_acc(rowsum, m)));
+  r.norm1 = gmax<UT>(i < U ? rowsum * (1.f / kRowScale) : 0.f);
   // with fewer slots than groups (PD items of one 32-lane system) the freed
   // registers raise occupancy, so the inverse reads L from LDS there
   // with a slot per system, the 32 x 32 forms run their two block products

@@ -258,16 +258,14 @@ struct SymSolve {
 // read row i of X back.
 template <int UT, class SM>
 __device__ __forceinline__ void sym_factor(SymSolve<UT> &r, SM &sm, int slot, int i, int U) {
-  bool bad = false;
   float rowsum = 0.f;
 #pragma unroll
   for (int k = 0; k < UT; ++k) {
     r.f.a[k] = lds_el<UT>(sm.A[slot], i, k);
-    bad |= !finite2(r.f.a[k]);
-    rowsum += __builtin_amdgcn_sqrtf(r.f.a[k].x * r.f.a[k].x + r.f.a[k].y * r.f.a[k].y);
+    rowsum = abs_row_acc(rowsum, r.f.a[k]);
   }
-  r.bad = gany<UT>(bad);
-  r.norm1 = gmax<UT>(i < U ? rowsum : 0.f);
+  r.bad = gany<UT>(!isfinite(rowsum));
+  r.norm1 = gmax<UT>(i < U ? rowsum * (1.f / kRowScale) : 0.f);
   // with a slot per system, the 32 x 32 factor and inverse run their two
   // block products on MFMA through the slots (read above, free until X is
   // parked)

@@ -230,6 +230,14 @@ def test_cond_estimate_is_upper_bound():
     # exact for a scaled identity; diagonal case is ||A||_1 * sum 1/a_i
     D = np.diag([1.0, 10.0, 100.0]).astype(complex)[None]
     np.testing.assert_allclose(oracle.cond_estimate(D), 100.0 * 1.11, rtol=1e-14)
+    # complex off-diagonal by hand: A = [[2, 1+i], [1-i, 2]] has column sums of
+    # |Re| + |Im| equal to 4 and A^{-1} = [[2, -1-i], [-1+i, 2]] / 2 (trace 2);
+    # its eigenvalues 2 +- sqrt 2 give kappa_2 = 5.83 < 8
+    A2 = np.array([[2.0, 1 + 1j], [1 - 1j, 2.0]])[None]
+    np.testing.assert_allclose(oracle.cond_estimate(A2), 8.0, rtol=1e-14)
+    # between the modulus form of the 1-norm and sqrt 2 times it
+    mod = np.max(np.sum(np.abs(A), axis=-2), axis=-1) * np.real(np.trace(np.linalg.inv(A), axis1=-2, axis2=-1))
+    assert np.all(k >= mod * (1 - 1e-12)) and np.all(k <= np.sqrt(2) * mod * (1 + 1e-12))
 
 
 # ---------------------------------------------------------------- large-system statistics
