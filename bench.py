@@ -8,7 +8,9 @@ inputs stream from HBM rather than from the 256 MB Infinity Cache).  The
 headline `value` is partially-decentralised (PD) L-MMSE in FP32; every other
 form (FD fusion; split-BF16 MFMA Gram; BF16 / split-BF16 MFMA Gram with one
 refinement step) is timed the same way under "variants", and the split-BF16
-MFMA form is set against FP32 under "bf16_mfma_vs_fp32".  Inputs are resident in HBM before timing starts.
+MFMA form is set against FP32 under "bf16_mfma_vs_fp32".  Inputs are resident in HBM before timing starts,
+and about 0.2 s of untimed calls of each form (`settle_s`) precede its warmup steps, so that the timed
+steps run at the device's loaded clocks.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--frames F]
 """
@@ -29,6 +31,8 @@ sys.path.insert(0, ROOT)
 B, C, U, W_FRAME, SNR_DB = 256, 8, 16, 1200, 10.0
 HBM_PEAK_GBS = 8000.0
 CPU_MIN_SECONDS = 10.0
+SETTLE_S = 0.2  # untimed load before each timed form (see settle)
+_SETTLE_S = [SETTLE_S]  # the run's value (--settle-s)
 
 
 def bytes_per_system(B=B, U=U):
@@ -157,33 +161,50 @@ class CpuBaseline:
         cpu = sum(r[3] for r in res)
         return {"value": n / span, "unit": "subcarriers/s", "cores": len(shares), "kind": "oracle",
                 "cpu_model": cpu_model(),
-                "sample": f"PD L-MMSE, complex128 NumPy oracle, {len(shares)} worker processes with one "
-                          f"thread each over the step's {self.frames} frames x {W_FRAME} subcarriers "
-                          f"(B={B}, C={C}, U={U}), each worker repeating its frames for about "
-                          f"{self.seconds:g} s: {n} systems in {span:.1f} s wall, {cpu:.1f} s CPU"}
+                "sample": f"PD L-MMSE complex128 NumPy oracle, {len(shares)} processes x 1 thread over the "
+                          f"step's {self.frames} x {W_FRAME} subcarriers, ~{self.seconds:g} s each: {n} "
+                          f"systems in {span:.1f} s wall, {cpu:.1f} s CPU"}
 
     def close(self):
         self.pool.terminate()
         self.pool.join()
 
 
-COMPACT_VARIANT_KEYS = ("call_ms_mean", "hbm_frac", "parity_max_rel_err_z")
+COMPACT_VARIANT_KEYS = ("call_ms_mean", "hbm_frac")
+COMPACT_BF16_KEYS = ("form", "speedup", "hbm_frac", "parity_max_rel_err_z")
+COMPACT_DROP_ROOFLINE = ("alg_bytes_per_system", "call_GBps")
 
 
 def compact_record(out, full_path=None):
     """The driver-facing last line: the headline, its roofline and the CPU
     baseline, the BF16-MFMA comparison and one short entry per timed form
     (the full record, with every other workload, goes to `full_path`)."""
-    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "settle_s", "ms_per_step", "higher_is_better",
             "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline",
             "bf16_mfma_vs_fp32")
     rec = {k: out[k] for k in keys if k in out}
-    rec["forms"] = {k: {kk: (round(v[kk], 7) if isinstance(v.get(kk), float) else v.get(kk))
-                        for kk in COMPACT_VARIANT_KEYS if kk in v}
-                    for k, v in out.get("variants", {}).items()}
+    if "roofline" in rec:
+        rec["roofline"] = {k: v for k, v in rec["roofline"].items() if k not in COMPACT_DROP_ROOFLINE}
+    if "bf16_mfma_vs_fp32" in rec:
+        rec["bf16_mfma_vs_fp32"] = {m: {k: v for k, v in c.items() if k in COMPACT_BF16_KEYS}
+                                    for m, c in rec["bf16_mfma_vs_fp32"].items()}
+    rec["forms_fields"] = list(COMPACT_VARIANT_KEYS)
+    rec["forms"] = {k: [v.get(kk) for kk in COMPACT_VARIANT_KEYS] for k, v in out.get("variants", {}).items()}
     if full_path:
         rec["full_record"] = os.path.relpath(full_path, ROOT) if full_path.startswith(ROOT) else full_path
-    return rec
+    return _round_floats(rec)
+
+
+def _round_floats(x, sig=5):
+    """Floats to `sig` significant digits (the compact line stays under 2 KB,
+    the driver keeps only the end of the output)."""
+    if isinstance(x, float):
+        return float(f"{x:.{sig}g}")
+    if isinstance(x, dict):
+        return {k: _round_floats(v, sig) for k, v in x.items()}
+    if isinstance(x, list):
+        return [_round_floats(v, sig) for v in x]
+    return x
 
 
 VARIANTS = [("pd", "fp32"), ("pd", "bf16x3"), ("pd", "bf16_refine"), ("pd", "bf16x3_refine"),
@@ -207,11 +228,33 @@ def _per_call(fn, steps):
     return np.array([e0.elapsed_time(e1) for e0, e1 in ev])
 
 
+def settle(fn, seconds):
+    """Untimed calls of `fn` for about `seconds` of wall time, before a form is
+    timed.  The GPU raises its clocks only after several milliseconds of
+    sustained load; after host-side work (input generation, the previous
+    form's oracle check: the device idle for up to seconds) a form's few
+    warmup steps and short timed region would otherwise run at the idle
+    clocks (about 15% slower for PD FP32, which a second pass of the same
+    calls does not show)."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        for _ in range(16):
+            fn()
+        n += 16
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return n
+
+
 def _timed(fn, steps, warmup):
     """Mean time per call (ms) of `steps` back-to-back calls between one pair
     of HIP events on the current stream, plus median / p10 / p90 of calls
     timed one by one."""
     import torch
+    if _SETTLE_S[0] > 0:
+        settle(fn, _SETTLE_S[0])
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -585,9 +628,13 @@ def main(argv=None):
                          "matrix instead of the headline workload (for focused profiles)")
     ap.add_argument("--workload", choices=["headline", "b1024", "ragged", "adjoint"], default="headline",
                     help="time one other workload alone (focused profiles; not the headline metric)")
+    ap.add_argument("--settle-s", type=float, default=SETTLE_S,
+                    help="seconds of untimed calls of each form before its warmup steps, so "
+                         "that the timed steps run at the device's loaded clocks (0 = none)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (PMC scale reference)")
     args = ap.parse_args(argv)
+    _SETTLE_S[0] = args.settle_s
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X: the equaliser is data-parallel over subcarriers "
@@ -644,6 +691,8 @@ def _gpu_main(args, cpu):
         def step():
             fn(H, y, n0, off, precision=prec, out=(z, s2, info), ws=ws)
 
+        if args.settle_s > 0:
+            settle(step, args.settle_s)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -713,23 +762,23 @@ def _gpu_main(args, cpu):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": args.settle_s,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"PD L-MMSE, B={B} antennas in C={C} clusters of {B // C}, U={U}, "
-                               f"{args.frames} frames x {W_FRAME} subcarriers = {W} systems per step, "
-                               f"16-QAM, SNR {SNR_DB:g} dB, i.i.d. Rayleigh",
+        "config": {"workload": f"PD L-MMSE, B={B} (C={C} x {B // C}), U={U}, {args.frames} x {W_FRAME} = {W} "
+                               f"subcarriers per step, 16-QAM, {SNR_DB:g} dB, i.i.d. Rayleigh",
                    "B": B, "C": C, "U": U, "systems_per_step": W, "form": head_key},
         "roofline": {"bound": "hbm", "achieved": head["kernel_alg_GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["kernel_hbm_frac"],
                      "traffic": traffic,
                      "kernel": "eq_forward_kernel<16, FP32, PD>",
                      "kernel_us_mean": head["kernel_ms_mean"] * 1e3,
-                     "timing": f"library HIP events around the kernel on its stream, "
-                               f"{head['kernel_launches_timed']} launches (a second pass of the timed steps)",
+                     "timing": f"kernel-timer HIP events on its stream, {head['kernel_launches_timed']} "
+                               f"launches (second pass)",
                      "alg_bytes_per_launch": launch_bytes,
                      "alg_bytes_per_system": bps,
                      "call_GBps": head["alg_GBps"], "call_frac": head["hbm_frac"],
