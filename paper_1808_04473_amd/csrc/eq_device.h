@@ -796,6 +796,71 @@ __device__ __forceinline__ void inverse32_split(Factor<32> &f, int u, float2 *ba
   });
 }
 
+// The same two forms in halves, for callers whose U may leave padded users
+// in a 32-lane group (the FD forms): the first 16 steps with the block
+// products, then steps 16 .. KE-1 with the updates restricted to the first KE
+// rows and columns.  For KE = 24 the rows 24..31 must be padding: users past
+// U, whose rows of A are the identity (zero Gram entries, 1 on the diagonal),
+// so their rows of L and X are the identity too and the 8 steps left out
+// would only scale them by 1.
+__device__ __forceinline__ int cholesky32_first(Factor<32> &f, int i, float2 *base) {
+  i = opaque_idx(i);
+  int fail = 0;
+  sfor<16>([&](auto J) { chol_step<32, J, 16>(f, i, fail); });
+  schur32_mfma(f, i, base);
+  return fail;
+}
+
+template <int KE>
+__device__ __forceinline__ void cholesky32_second(Factor<32> &f, int i, int &fail) {
+  i = opaque_idx(i);
+  sfor<KE - 16>([&](auto J) {
+    constexpr int j = J;
+    chol_step<32, j + 16, KE>(f, i, fail);
+  });
+  if constexpr (KE < 32) {
+    if (i >= KE) f.dinv = 1.f;
+  }
+}
+
+__device__ __forceinline__ void inverse32_first(Factor<32> &f, int u, float2 *base) {
+  u = opaque_idx(u);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+  sfor<16>([&](auto J) { inv_step<32, J, 16>(f); });
+  const int lane = lane_id();
+  float2 *W = base + (lane / 32) * 1024;
+  if (u < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) W[kSplitM + k * kSplitStride + u] = f.x[k];
+  }
+  __syncthreads();
+  const int lr = lane % 16, lg = lane / 16;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float2 *Ws = base + s * 1024;
+    f4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+    auto ga = [&](int kc) { return Ws[lr * kSplitStride + 4 * kc + lg]; };
+    auto gb = [&](int kc) { return Ws[kSplitM + (4 * kc + lg) * kSplitStride + lr]; };
+    cmma16(re, im, ga, gb, true);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ws[kSplitY + (4 * lg + r) * kSplitStride + lr] = make_float2(re[r], im[r]);
+  }
+  __syncthreads();
+  if (u < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f.x[16 + k] = W[kSplitY + k * kSplitStride + u];
+  }
+}
+
+template <int KE>
+__device__ __forceinline__ void inverse32_second(Factor<32> &f) {
+  sfor<KE - 16>([&](auto J) {
+    constexpr int j = J;
+    inv_step<32, j + 16, KE>(f);
+  });
+}
+
 // The same inverse with L read from LDS instead of registers: Ls holds L
 // (row i written by lane i) with 1 / L_jj on the diagonal, and every lane of
 // a group reads the same element (an LDS broadcast).  The rows of L in
@@ -865,9 +930,31 @@ __device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
 //
 // Ls (optional) is the LDS matrix slot the system was loaded from: with it,
 // 32-lane groups store L there and form the inverse from LDS.
-template <int UT>
+//
+// PAD: U (wave-uniform) may leave padded users; with at most 24 users the
+// 32 x 32 forms then leave out the last 8 steps.
+template <int UT, bool PAD = false>
 __device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail,
-                                               float2 (*Ls)[UT] = nullptr, float2 *split = nullptr) {
+                                               float2 (*Ls)[UT] = nullptr, float2 *split = nullptr,
+                                               int U = UT) {
+  if constexpr (UT == 32 && PAD) {
+    if (split) {
+      const bool u24 = __builtin_amdgcn_readfirstlane(U) <= 24;
+      fail = cholesky32_first(f, i, split);
+      if (u24)
+        cholesky32_second<24>(f, i, fail);
+      else
+        cholesky32_second<32>(f, i, fail);
+      const float2 t = fwd_subst<UT>(f, i, m);
+      asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));
+      inverse32_first(f, i, split);
+      if (u24)
+        inverse32_second<24>(f);
+      else
+        inverse32_second<32>(f);
+      return apply_xh<UT>(f, t);
+    }
+  }
   if constexpr (UT == 32) {
     if (split) {
       // the wave's systems each own an LDS matrix slot (split: the first)

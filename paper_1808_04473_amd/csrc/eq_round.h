@@ -37,7 +37,10 @@ struct LocalSolve {
   bool bad;
 };
 
-template <int UT, class SM>
+// PAD: with at most 24 users in a 32-lane group, leave out the steps of the
+// factorisation and inverse that only touch the padded users (the FD forms,
+// which solve one system per cluster; PD measured no faster).
+template <int UT, bool PAD = false, class SM>
 __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, int i, int U) {
   float rowsum = 0.f;
 #pragma unroll
@@ -54,7 +57,7 @@ __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, 
   // on MFMA through the slots (read above, free until the solve ends)
   float2 *split = nullptr;
   if constexpr (UT == 32 && SM::NS == SM::NSYS) split = &sm.A[0][0][0];
-  r.z = factor_solve<UT>(r.f, i, m, r.fail, SM::NS < SM::NSYS ? sm.A[sme] : nullptr, split);
+  r.z = factor_solve<UT, PAD>(r.f, i, m, r.fail, SM::NS < SM::NSYS ? sm.A[sme] : nullptr, split, U);
   r.d = inv_diag<UT>(r.f);
 }
 
