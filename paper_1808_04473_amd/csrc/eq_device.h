@@ -672,6 +672,26 @@ __device__ __forceinline__ void inverse_columns(Factor<UT> &f, int u) {
   sfor<UT>([&](auto J) { inv_step<UT, J, UT>(f); });
 }
 
+// The factorisation and inverse of a system whose rows KE..UT-1 are padding
+// (users past U: identity rows of A, so identity rows of L and X): the first
+// KE steps, with the updates restricted to the first KE rows and columns.
+template <int UT, int KE>
+__device__ __forceinline__ int cholesky_pad(Factor<UT> &f, int i) {
+  i = opaque_idx(i);
+  int fail = 0;
+  sfor<KE>([&](auto J) { chol_step<UT, J, KE>(f, i, fail); });
+  if (i >= KE) f.dinv = 1.f;
+  return fail;
+}
+
+template <int UT, int KE>
+__device__ __forceinline__ void inverse_columns_pad(Factor<UT> &f, int u) {
+  u = opaque_idx(u);
+#pragma unroll
+  for (int j = 0; j < UT; ++j) f.x[j] = make_float2(u == j ? 1.f : 0.f, 0.f);
+  sfor<KE>([&](auto J) { inv_step<UT, J, KE>(f); });
+}
+
 // ---- 32 x 32: the two 16 x 16 x 16 products of the blocked forms on MFMA
 // With A = [A11 A12; A21 A22] in 16 x 16 blocks, the Cholesky factor is
 // L11 = chol(A11), L21 = A21 L11^{-H}, L22 = chol(A22 - L21 L21^H), and the
@@ -931,13 +951,23 @@ __device__ __forceinline__ float2 apply_xh(const Factor<UT> &f, float2 t) {
 // Ls (optional) is the LDS matrix slot the system was loaded from: with it,
 // 32-lane groups store L there and form the inverse from LDS.
 //
-// PAD: U (wave-uniform) may leave padded users; with at most 24 users the
-// 32 x 32 forms then leave out the last 8 steps.
-template <int UT, bool PAD = false>
+// PAD: U (wave-uniform) may leave padded users; the 32 x 32 forms (PAD & 1)
+// then leave out the last 8 steps for at most 24 users, the 16 x 16 forms
+// (PAD & 2) the last 8 for at most 8 users.
+template <int UT, int PAD = 0>
 __device__ __forceinline__ float2 factor_solve(Factor<UT> &f, int i, float2 m, int &fail,
                                                float2 (*Ls)[UT] = nullptr, float2 *split = nullptr,
                                                int U = UT) {
-  if constexpr (UT == 32 && PAD) {
+  if constexpr (UT == 16 && (PAD & 2)) {
+    if (__builtin_amdgcn_readfirstlane(U) <= 8) {
+      fail = cholesky_pad<UT, 8>(f, i);
+      const float2 t = fwd_subst<UT>(f, i, m);
+      asm volatile("" : "+v"(f.a[0].x) : "v"(t.x), "v"(t.y));
+      inverse_columns_pad<UT, 8>(f, i);
+      return apply_xh<UT>(f, t);
+    }
+  }
+  if constexpr (UT == 32 && (PAD & 1)) {
     if (split) {
       const bool u24 = __builtin_amdgcn_readfirstlane(U) <= 24;
       fail = cholesky32_first(f, i, split);

@@ -147,7 +147,7 @@ __device__ __forceinline__ void fd_task(const FwdArgs &a, int w0, int nsub, SM &
     const int w = w0 + wl;
     const bool live = sme < nvalid;
     LocalSolve<UT> r;
-    local_solve<UT, true>(r, sm, sme, i, a.U);
+    local_solve<UT, 1>(r, sm, sme, i, a.U);
     if constexpr (refines(PREC)) refine_round<UT>(r, sm, nvalid, a.U, [&](int) { return a.rho; }, seg, live);
 
     const float kappa = r.norm1 * gsum<UT>(i < a.U ? r.d : 0.f);

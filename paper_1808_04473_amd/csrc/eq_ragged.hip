@@ -196,7 +196,7 @@ __device__ __forceinline__ void fd_round(const RaggedArgs &a, const RTask &task,
   __syncthreads();
   const bool live = sme < n;
   LocalSolve<UT> r;
-  local_solve<UT, true>(r, sm, sme, i, U);
+  local_solve<UT, 3>(r, sm, sme, i, U);
   if constexpr (refines(PREC))
     refine_round<UT>(r, sm, n, U, [&](int s) { return a.sys[sysk(s)].rho; }, seg, live);
   const float kappa = r.norm1 * gsum<UT>(i < U ? r.d : 0.f);

@@ -37,10 +37,11 @@ struct LocalSolve {
   bool bad;
 };
 
-// PAD: with at most 24 users in a 32-lane group, leave out the steps of the
-// factorisation and inverse that only touch the padded users (the FD forms,
-// which solve one system per cluster; PD measured no faster).
-template <int UT, bool PAD = false, class SM>
+// PAD (factor_solve): leave out the steps of the factorisation and inverse
+// that only touch padded users, for at most 24 users in a 32-lane group
+// (PAD & 1) or 8 in a 16-lane group (PAD & 2); the FD forms, which solve one
+// system per cluster, use it (PD measured no faster).
+template <int UT, int PAD = 0, class SM>
 __device__ __forceinline__ void local_solve(LocalSolve<UT> &r, SM &sm, int sme, int i, int U) {
   float rowsum = 0.f;
 #pragma unroll
