@@ -822,7 +822,9 @@ __device__ __forceinline__ void inverse32_split(Factor<32> &f, int u, float2 *ba
 // rows and columns.  For KE = 24 the rows 24..31 must be padding: users past
 // U, whose rows of A are the identity (zero Gram entries, 1 on the diagonal),
 // so their rows of L and X are the identity too and the 8 steps left out
-// would only scale them by 1.
+// would only scale them by 1.  cholesky32_split and inverse32_split keep their
+// own copies of the first halves: built from these pieces, the PD kernels
+// (which never take the short form) ran 1-2% slower.
 __device__ __forceinline__ int cholesky32_first(Factor<32> &f, int i, float2 *base) {
   i = opaque_idx(i);
   int fail = 0;
