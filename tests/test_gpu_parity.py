@@ -102,6 +102,8 @@ SHAPES = [
     (2, 300, 8, [0, 100, 300]),
     (5, 40, 6, list(range(0, 41, 2))),      # C = 20 > 16: FD rounds span subcarriers
     (3, 68, 16, list(range(0, 69, 4))),     # C = 17, B_c = 4 < U = 16
+    (4, 64, 23, [0, 30, 64]),              # UT = 32 with 9 padded users (the short FD solve)
+    (4, 64, 25, [0, 34, 64]),              # UT = 32 with 7 padded users (the full solve)
 ]
 
 

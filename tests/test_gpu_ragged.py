@@ -225,6 +225,8 @@ EXTREME = [
     (8, [16] * 64), (16, [32] * 40), (32, [40] * 24),      # clusters over many rounds
     (1, [3, 5]), (17, [20, 18, 30]), (2, [1, 1, 1]),       # U = 1, 17, one-row clusters
     (32, [64] * 60), (16, [256] * 4),                      # B = 3840 and 1024: many pieces
+    (7, [12, 20]), (9, [20, 24]), (23, [30, 26]), (25, [40, 36]),  # either side of the short
+                                                           # FD solves (U <= 8 of 16, U <= 24 of 32)
 ]
 
 
@@ -232,8 +234,9 @@ EXTREME = [
 @pytest.mark.parametrize("rows", [None, 32], ids=["tuned", "pieces32"])
 def test_ragged_extreme_shapes(fd, rows, tmp_path):
     """Single-cluster FD systems, systems whose 24-64 clusters span many
-    rounds, U = 1 and 17, one-row clusters, and systems cut into up to 120
-    row pieces: every system against the oracle."""
+    rounds, U = 1 and 17, one-row clusters, systems cut into up to 120 row
+    pieces, and U = 7, 9, 23, 25 around the widths where FD leaves out the
+    padded users' steps: every system against the oracle."""
     from paper_1808_04473_amd import api
     rb = _custom_batch(EXTREME)
     cache = tmp_path / "t.json"
